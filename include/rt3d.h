@@ -1,0 +1,264 @@
+/*
+ * rt3d.h -- C ABI of the MI355X Monte Carlo solar photon tracer.
+ *
+ * The library traces solar photon packets through a 3D grid of gas and cloud
+ * optical properties and returns per-cell absorption (heating) and
+ * direct/diffuse surface irradiance tallies.  The method is the forward
+ * Monte Carlo ray tracer of Veerman, van Stratum and van Heerwaarden,
+ * "Shallow cumulus convection over land in cloud-resolving simulations with
+ * a coupled ray tracer" (GRL 2022), section 2.3 "The ray tracer":
+ *   - inputs: 3D fields of total extinction k_ext, cloud extinction
+ *     k_ext,cloud, single-scattering albedo omega0 and asymmetry g (sec. 2.3,
+ *     the paragraph on required inputs);
+ *   - photons enter at the top of the domain (TOD) along the solar beam or,
+ *     with probability equal to the diffuse fraction, isotropically
+ *     downwards (sec. 2.3, initialisation paragraph);
+ *   - null-collision tracking on a one-level coarse acceleration grid whose
+ *     cells hold the maximum fine-cell extinction (sec. 2.3, acceleration
+ *     grid paragraph);
+ *   - Rayleigh scattering by gas, Henyey-Greenstein scattering (no delta
+ *     scaling) by cloud droplets, cloud chosen with probability
+ *     k_ext,cloud / k_ext (sec. 2.3, phase-function paragraph);
+ *   - absorption by weights at every scattering or null-collision event,
+ *     the removed weight stored as heating; Russian roulette below weight
+ *     0.5; Lambertian surface whose albedo scales the weight (sec. 2.3,
+ *     weights paragraph);
+ *   - surface and TOD fluxes are the summed weights of photons reaching the
+ *     surface or leaving the top; "direct" means never scattered (sec. 2.3
+ *     and sec. 3.3.1, definition of direct radiation).
+ *
+ * Every entry point is `extern "C"`, takes plain pointers and sizes, and
+ * reports errors only through `rt3d_status`.  Unless stated otherwise a
+ * pointer argument is a DEVICE pointer owned by the caller; the library
+ * never allocates or frees device memory.  `stream` is a hipStream_t passed
+ * as `void*` (NULL = the null stream).  All work is enqueued asynchronously
+ * on `stream`; results are valid once that stream has completed.  Host-side
+ * argument checks run before anything is enqueued, so a call that returns an
+ * error has launched nothing (except RT3D_EDOMAIN, see RT3D_FLAG_VALIDATE).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions
+ * ---------------------------------------------------------------------------
+ * Grid: nx x ny x nz cells of size dx x dy x dz metres.  x points east, y
+ * north, z up; the domain is [0, nx*dx) x [0, ny*dy) x [0, nz*dz] with
+ * periodic x and y boundaries, an open top at z = H = nz*dz (a photon moving
+ * up through it escapes for good) and the surface at z = 0.
+ * 3D arrays are [nz][ny][nx] with x fastest (cell (i,j,k) at
+ * (k*ny + j)*nx + i); 2D arrays are [ny][nx].
+ *
+ * Sun: zenith angle sza in [0, 90) degrees; azimuth measured clockwise from
+ * north (+y), the direction the sun is seen in.  Photons travel along
+ *   d0 = (-sin(sza) sin(az), -sin(sza) cos(az), -cos(sza)).
+ *
+ * Weights: a photon packet carries an integer weight in units of 2^-31 of
+ * the initial weight (W1 = 2^31 = weight one).  Every tally and every entry
+ * of the energy ledger is a uint64 sum of such integers, so tallies are
+ * exact, independent of the order of atomic updates, bitwise reproducible,
+ * and the energy budget closes exactly (see RT3D_LEDGER_*).
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11),
+ * key = (seed & 0xffffffff, seed >> 32).  For photon index id (counted from
+ * 0 over the whole run, so `photon_offset` + local index) with
+ * id_lo/id_hi its 32-bit halves, counters are:
+ *   run offset      (0, 0, 0xfffffffe, 0)        word 0 -> column offset o
+ *   emission        (id_lo, id_hi, 0xffffffff, 0) words 0,1 -> x, y inside
+ *                                                 the column, word 2 ->
+ *                                                 diffuse/direct choice
+ *   diffuse entry   (id_lo, id_hi, 0xffffffff, 1) words 0,1 -> mu^2, phi
+ *   free path s     (id_lo, id_hi, s, 0)          word 0 -> optical depth,
+ *                                                 word 1 -> event choice,
+ *                                                 word 2 -> cos(theta) or
+ *                                                 surface mu^2, word 3 -> phi
+ *   roulette at s   (id_lo, id_hi, s, 1)          word 0 -> rho
+ * s counts the free paths of one photon from 0.  Photon id enters column
+ * c = (id + o) mod (nx*ny), cell (c mod nx, c div nx) (systematic sampling:
+ * every column receives floor or ceil of photons/(nx*ny) photons).
+ */
+#ifndef RT3D_H
+#define RT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT3D_ABI_VERSION 1
+
+typedef enum {
+    RT3D_OK = 0,
+    RT3D_EINVAL = 1,  /* bad argument: null pointer, non-positive size, brick
+                         not dividing the grid, sza outside [0,90), photons 0,
+                         workspace too small, too many cells */
+    RT3D_EDOMAIN = 2, /* RT3D_FLAG_VALIDATE found a field value out of range */
+    RT3D_EDEVICE = 3  /* a HIP runtime call failed; see rt3d_last_device_error */
+} rt3d_status;
+
+/* Uniform grid; every size positive, nx*ny*nz < 2^31. */
+typedef struct {
+    int32_t nx, ny, nz;
+    float dx, dy, dz; /* metres */
+} rt3d_grid;
+
+/* Optical properties (sec. 2.3, required inputs), device pointers to FP32
+ * [nz][ny][nx] arrays:
+ *   k_ext        total extinction coefficient, m^-1, >= 0
+ *   k_ext_cloud  cloud-droplet extinction, m^-1, 0 <= k_ext_cloud <= k_ext
+ *   ssa          total single-scattering albedo omega0 in [0,1]
+ *   g            Henyey-Greenstein asymmetry of the cloud droplets in [-1,1]
+ *                (gas always scatters with the Rayleigh phase function)    */
+typedef struct {
+    const float* k_ext;
+    const float* k_ext_cloud;
+    const float* ssa;
+    const float* g;
+} rt3d_optical_props;
+
+/* Raw tallies, caller-owned device buffers of uint64 in units of 2^-31 of a
+ * photon's initial weight (see rt3d_finalize for physical units):
+ *   abs_dir [nz][ny][nx]  weight absorbed in the cell while never scattered
+ *   abs_dif [nz][ny][nx]  weight absorbed in the cell after scattering
+ *   sfc_dir [ny][nx]      weight reaching the surface unscattered (direct)
+ *   sfc_dif [ny][nx]      weight reaching the surface after scattering
+ *   sfc_abs [ny][nx]      weight absorbed by the surface
+ *   toa_up  [ny][nx]      weight leaving through the top of the domain
+ *   ledger  [RT3D_LEDGER_N] energy ledger (below)
+ *   stats   [RT3D_STATS_N]  event counters (below)                        */
+typedef struct {
+    uint64_t* abs_dir;
+    uint64_t* abs_dif;
+    uint64_t* sfc_dir;
+    uint64_t* sfc_dif;
+    uint64_t* sfc_abs;
+    uint64_t* toa_up;
+    uint64_t* ledger;
+    uint64_t* stats;
+} rt3d_tallies;
+
+/* Energy ledger.  For every run the identity
+ *   INCOMING + RR_GAIN == TOA + ATM_DIR + ATM_DIF + SFC + RR_LOSS + LOST
+ * holds exactly in integers; ATM_DIR == sum(abs_dir), ATM_DIF ==
+ * sum(abs_dif), SFC == sum(sfc_abs), TOA == sum(toa_up).                  */
+enum {
+    RT3D_LEDGER_INCOMING = 0, /* photons * 2^31 */
+    RT3D_LEDGER_TOA = 1,
+    RT3D_LEDGER_ATM_DIR = 2,
+    RT3D_LEDGER_ATM_DIF = 3,
+    RT3D_LEDGER_SFC = 4,
+    RT3D_LEDGER_RR_GAIN = 5,  /* weight added by roulette survivors */
+    RT3D_LEDGER_RR_LOSS = 6,  /* weight of photons ended by roulette */
+    RT3D_LEDGER_LOST = 7,     /* weight of photons stopped by max_iters */
+    RT3D_LEDGER_N = 8
+};
+
+/* Event counters.  A "photon event" (the throughput unit) is one tentative
+ * collision or one surface interaction: STAT_EVENTS = COLLISIONS + SURFACE. */
+enum {
+    RT3D_STAT_PHOTONS = 0,
+    RT3D_STAT_COLLISIONS = 1,   /* tentative (null + real) collisions */
+    RT3D_STAT_NULL = 2,
+    RT3D_STAT_SCAT_GAS = 3,
+    RT3D_STAT_SCAT_CLOUD = 4,
+    RT3D_STAT_SURFACE = 5,
+    RT3D_STAT_ESCAPE = 6,
+    RT3D_STAT_RR_KILL = 7,
+    RT3D_STAT_RR_SURVIVE = 8,
+    RT3D_STAT_CROSSINGS = 9,    /* acceleration-grid cell crossings */
+    RT3D_STAT_ABSORBED = 10,    /* photons whose weight reached exactly 0 */
+    RT3D_STAT_CAPPED = 11,      /* photons stopped by max_iters */
+    RT3D_STATS_N = 12
+};
+
+/* Flags for rt3d_options.flags */
+#define RT3D_FLAG_ACCUMULATE 0x1u /* add to the tallies instead of zeroing */
+#define RT3D_FLAG_VALIDATE 0x2u   /* check the fields on the device first
+                                     (synchronises the stream) */
+#define RT3D_FLAG_TIME 0x4u       /* time the tracing kernel with HIP events;
+                                     read with rt3d_last_trace_ms */
+
+typedef struct {
+    /* acceleration-grid cell ("brick") in fine cells; must divide nx, ny, nz */
+    int32_t brick_x, brick_y, brick_z;
+    float diffuse_fraction;  /* probability of an isotropic diffuse entry */
+    float rr_threshold;      /* roulette below this weight (paper: 0.5); 0 = off */
+    uint32_t flags;
+    uint32_t max_iters;      /* per-photon cap on collisions + surface hits +
+                                brick crossings; the rest of its weight goes to
+                                RT3D_LEDGER_LOST.  0 = default (1<<24) */
+    uint64_t photon_offset;  /* first photon id of this call (chunked runs) */
+    int32_t grid_blocks;     /* persistent workgroups, 0 = automatic */
+    int32_t block_threads;   /* threads per workgroup, 0 = automatic */
+} rt3d_options;
+
+/* ---------------------------------------------------------------------- */
+
+/* ABI version (RT3D_ABI_VERSION). */
+int rt3d_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char* rt3d_status_string(rt3d_status s);
+
+/* Text of the last HIP error seen by the calling thread ("" if none). */
+const char* rt3d_last_device_error(void);
+
+/* Fill *opt with defaults: brick 8x8x8 clamped to the grid by the trace call
+ * when 0, diffuse_fraction 0, rr_threshold 0.5, no flags, max_iters 1<<24,
+ * photon_offset 0, automatic launch shape.  Host pointer. */
+void rt3d_default_options(rt3d_options* opt);
+
+/* Bytes of device workspace rt3d_trace needs for this grid and options
+ * (majorant grid, work-queue counter and flags).  Returns 0 on bad input. */
+size_t rt3d_workspace_size(const rt3d_grid* grid, const rt3d_options* opt);
+
+/* Acceleration grid (sec. 2.3, acceleration grid paragraph): majorant[b] =
+ * max of k_ext over the fine cells of brick b, exactly (FP32 max).
+ * majorant: device FP32 [nz/bz][ny/by][nx/bx].  k_ext must be >= 0. */
+rt3d_status rt3d_majorant_build(const rt3d_grid* grid, const float* k_ext,
+                                int32_t bx, int32_t by, int32_t bz,
+                                float* majorant, void* stream);
+
+/* Trace `photons` photon packets (sec. 2.3) entering the top of the domain
+ * with the sun at (sza_deg, azimuth_deg) and write raw tallies to `out`
+ * (zeroed first unless RT3D_FLAG_ACCUMULATE).  surface_albedo: device FP32
+ * [ny][nx] in [0,1].  seed: Philox key.  opt: host pointer or NULL for
+ * defaults.  workspace: device buffer of at least rt3d_workspace_size bytes,
+ * 256-byte aligned; its contents need not be initialised.  Same inputs and
+ * seed give bitwise-identical tallies; calls over disjoint photon_offset
+ * ranges with ACCUMULATE sum to exactly the single-call result. */
+rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props,
+                       const float* surface_albedo, double sza_deg,
+                       double azimuth_deg, uint64_t photons, uint64_t seed,
+                       const rt3d_options* opt, const rt3d_tallies* out,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* Milliseconds spent in the tracing kernel of the last rt3d_trace call made
+ * with RT3D_FLAG_TIME on this thread (waits for it to finish).  Host *ms. */
+rt3d_status rt3d_last_trace_ms(float* ms);
+
+/* Normalise raw tallies (sec. 2.3: fluxes are mean weights; heating is the
+ * absorbed weight) for a run of `photons` photons: every tally is divided by
+ * (photons / (nx*ny)) * 2^31, giving fractions of the downward flux at the
+ * top of the domain per column area.  3D outputs are then multiplied by
+ * layer_scale[k] (FP64 device [nz], NULL = 1), 2D outputs by flux_scale; e.g.
+ * layer_scale = F_TOD*86400/(rho_k*c_p*dz) turns absorption into heating
+ * rates in K/day and flux_scale = F_TOD turns fluxes into W/m^2.  Any output
+ * pointer may be NULL to skip it.  Outputs: FP32 device arrays shaped like
+ * the matching raw tallies.  raw: the tallies written by rt3d_trace. */
+rt3d_status rt3d_finalize(const rt3d_grid* grid, const rt3d_tallies* raw,
+                          uint64_t photons, const double* layer_scale,
+                          double flux_scale, float* abs_dir, float* abs_dif,
+                          float* sfc_dir, float* sfc_dif, float* sfc_abs,
+                          float* toa_up, void* stream);
+
+/* Philox4x32-10 as used by the tracer, for bit-level tests: for each of n
+ * counters ctr[4*i .. 4*i+3] (device uint32) write the four output words to
+ * out[4*i .. 4*i+3] (device uint32), key = (seed lo, seed hi). */
+rt3d_status rt3d_philox4x32_10(const uint32_t* ctr, uint64_t seed,
+                               uint32_t* out, uint32_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT3D_H */

@@ -1,0 +1,147 @@
+"""Throughput benchmark of the MI355X photon tracer.
+
+One step = one pass of the whole hot path over one batch of synthetic input:
+rt3d_trace (tally clearing, majorant build, persistent tracing kernel) and
+rt3d_finalize (normalisation) for 2^26 photons through the 256x256x128
+LES-shaped cumulus field (50 x 50 x 25 m cells, 200 Gaussian cloud blobs,
+SZA 45 deg, 8x8x8 acceleration-grid cells).  Inputs are resident in HBM
+before timing starts.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photon events/s + time to 5% heating-rate RMS, plain vs batched+denoised"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per event of the tracing kernel (random gathers and
+# tally read-modify-writes at the method's granularity; majorants live in
+# LDS/L1 and are not counted):
+#   tentative collision: 8 B (k_ext, ssa) + 8 B heating-tally update
+#   real scattering:     + 4 B (k_ext_cloud); cloud scattering: + 4 B (g)
+#   surface hit:         4 B albedo + 8 B irradiance + 8 B absorbed tally
+#   escape:              8 B TOD tally
+def algorithmic_bytes(stats) -> float:
+    s = {k: float(v) for k, v in stats.items()}
+    return (16.0 * s["collisions"] + 4.0 * (s["scat_gas"] + s["scat_cloud"]) + 4.0 * s["scat_cloud"]
+            + 20.0 * s["surface"] + 8.0 * s["escape"])
+
+
+def cpu_baseline(wl, target_s: float = 12.0) -> dict:
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    n = 1 << 16
+    t0 = time.perf_counter()
+    oracle.trace(wl.fields, wl.sza, wl.azimuth, n, 123, brick=wl.brick, nthreads=threads)
+    dt = time.perf_counter() - t0
+    n2 = n
+    while n2 < (1 << 24) and dt * (n2 * 2) / n < target_s:
+        n2 *= 2
+    t0 = time.perf_counter()
+    r = oracle.trace(wl.fields, wl.sza, wl.azimuth, n2, 123, brick=wl.brick, nthreads=threads)
+    dt = time.perf_counter() - t0
+    st = dict(zip(oracle.STATS, r["stats"].tolist()))
+    ev = st["collisions"] + st["surface"]
+    return {"value": ev / dt, "unit": "photon events/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n2} photons of the same 256x256x128 cumulus workload (FP64 C oracle, "
+                      f"{threads} threads, {dt:.1f} s, {ev / n2:.1f} events/photon)",
+            "photons_per_s": n2 / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=int, default=1 << 26)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lds-majorant", type=int, default=0)
+    ap.add_argument("--brick", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the tracer is single-GPU (photons or g-points would be "
+              "sharded across GPUs with one all-reduce of the tallies; not built here)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_05247_amd import rt3d
+    from paper_2208_05247_amd import synthetic as syn
+
+    wl = syn.les_cumulus(photons=args.photons, brick=(args.brick,) * 3)
+    grid = wl.fields.grid
+    df = rt3d.DeviceFields.from_host(wl.fields, "cuda")
+    out = rt3d.alloc_tallies(grid)
+    opt = rt3d.options(brick=wl.brick)
+    ws = rt3d.alloc_workspace(rt3d.workspace_size(grid, opt))
+
+    def step(seed):
+        raw = rt3d.trace(df, wl.sza, wl.azimuth, wl.photons, seed, brick=wl.brick, out=out, workspace=ws,
+                         timed=True, lds_majorant=args.lds_majorant)
+        kms = rt3d.last_trace_ms()
+        fin = rt3d.finalize(grid, raw, wl.photons)
+        return kms, raw["stats"].clone(), fin
+
+    for w in range(args.warmup):
+        step(1000 + w)
+    torch.cuda.synchronize()
+    kernel_ms, stats = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        kms, st, _ = step(k + 1)
+        kernel_ms.append(kms)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    tot = {n: 0 for n in rt3d.STATS}
+    for st in stats:
+        for n, v in zip(rt3d.STATS, st.cpu().tolist()):
+            tot[n] += v
+    events = tot["collisions"] + tot["surface"]
+    ms_per_step = wall * 1e3 / args.steps
+    mean_kms = sum(kernel_ms) / len(kernel_ms)
+    bytes_per_launch = algorithmic_bytes(tot) / args.steps
+    achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": events / wall,
+        "unit": "photon events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": [grid.nx, grid.ny, grid.nz],
+                   "cell_m": [grid.dx, grid.dy, grid.dz], "photons_per_step": wl.photons,
+                   "photons_per_column": wl.photons // grid.ncol, "sza_deg": wl.sza,
+                   "brick": list(wl.brick), "parallelism": "single GPU"},
+        "photons_per_s": tot["photons"] / wall,
+        "events_per_photon": events / max(1, tot["photons"]),
+        "trace_kernel_ms": mean_kms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "trace_kernel",
+                     "bytes_per_launch": bytes_per_launch},
+        "paper_context": "A100 40GiB: ~1.9e8 photons/s derived from 90 s for 112 g-points x 256 "
+                         "photons/column on 768x768 columns (different fields)",
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,8 @@ typedef struct {
     uint64_t photon_offset;  /* first photon id of this call (chunked runs) */
     int32_t grid_blocks;     /* persistent workgroups, 0 = automatic */
     int32_t block_threads;   /* threads per workgroup, 0 = automatic */
+    int32_t lds_majorant;    /* stage the majorant grid in LDS: 0 = automatic,
+                                1 = when it fits, -1 = never */
 } rt3d_options;
 
 /* ---------------------------------------------------------------------- */

@@ -1,0 +1,832 @@
+// rt3d.hip -- Monte Carlo solar photon tracer for gfx950 (MI355X) behind the
+// C ABI declared in include/rt3d.h.
+//
+// Method: the forward Monte Carlo ray tracer of Veerman, van Stratum and van
+// Heerwaarden (GRL 2022), sec. 2.3 -- null-collision tracking on a one-level
+// acceleration grid, absorption by weights at every scattering or null
+// collision, Rayleigh (gas) / Henyey-Greenstein (cloud) scattering, Russian
+// roulette below weight 0.5, Lambertian surface, heating and flux tallies.
+//
+// Design for CDNA4 (not the paper's CUDA design):
+//   * persistent kernel, one photon per lane, lanes refilled from a
+//     per-wave pool of photon ids that is topped up with one global atomic
+//     per pool, so divergent photon lifetimes do not idle the wave;
+//   * one loop pass = one acceleration-grid cell: either the tentative
+//     collision inside it, or a crossing into the next cell (surface / top
+//     handled at the crossing), so all lanes do comparable work per pass;
+//   * majorants staged in LDS when they fit, else read through L1/L2;
+//   * integer weights (units of 2^-31) and uint64 tallies: order-independent
+//     atomics, bitwise-reproducible results and an exactly closing ledger;
+//   * deposits into the same cell by consecutive events of one lane are
+//     merged in registers and written with one atomic when the lane moves on;
+//   * event counters live in registers and are folded into LDS per photon
+//     and into global memory once per workgroup.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <cmath>
+#include <mutex>
+
+#include "rt3d.h"
+
+namespace {
+
+constexpr uint32_t kWOne = 0x80000000u;  // weight one in units of 2^-31
+constexpr int kBlock = 256;              // threads per workgroup
+constexpr uint32_t kPool = 256;          // photon ids fetched per wave refill
+constexpr uint32_t kNoCell = 0xffffffffu;
+constexpr size_t kLdsMajorantBytes = 16 * 1024;  // automatic LDS staging limit
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): per round the counter becomes
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key
+// is bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// 24-bit uniforms: [0,1) for comparisons and positions, (0,1] for logs.
+__device__ __forceinline__ float u01(uint32_t u) { return (float)(u >> 8) * 0x1p-24f; }
+__device__ __forceinline__ float u01_open(uint32_t u) { return (float)((u >> 8) + 1u) * 0x1p-24f; }
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Henyey-Greenstein cos(theta) by inversion of its cumulative distribution.
+__device__ __forceinline__ float hg_cos(float g, float xi) {
+    if (fabsf(g) < 1e-3f) return 2.0f * xi - 1.0f;
+    const float s = (1.0f - g * g) / (1.0f - g + 2.0f * g * xi);
+    const float mu = (1.0f + g * g - s * s) / (2.0f * g);
+    return fminf(1.0f, fmaxf(-1.0f, mu));
+}
+
+// Rayleigh cos(theta): root of mu^3 + 3 mu + 4 - 8 xi = 0 (Cardano).
+__device__ __forceinline__ float rayleigh_cos(float xi) {
+    const float q = 4.0f * xi - 2.0f;
+    const float u = cbrtf(q + sqrtf(q * q + 1.0f));
+    return fminf(1.0f, fmaxf(-1.0f, u - rcp(u)));
+}
+
+// Turn direction (x,y,z) by polar cosine mu and azimuth 2*pi*t.
+__device__ __forceinline__ void turn(float& x, float& y, float& z, float mu, float t) {
+    float sp, cp;
+    __sincosf(6.28318530717958647f * t, &sp, &cp);
+    const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+    float nx, ny, nz;
+    if (fabsf(z) > 0.99999f) {
+        nx = st * cp;
+        ny = st * sp;
+        nz = z > 0.0f ? mu : -mu;
+    } else {
+        const float s = sqrtf(1.0f - z * z);
+        const float is = rcp(s);
+        nx = st * (x * z * cp - y * sp) * is + x * mu;
+        ny = st * (y * z * cp + x * sp) * is + y * mu;
+        nz = -st * cp * s + z * mu;
+    }
+    const float n = rsqrtf(nx * nx + ny * ny + nz * nz);
+    x = nx * n;
+    y = ny * n;
+    z = nz * n;
+}
+
+struct TraceParams {
+    const float* __restrict__ k_ext;
+    const float* __restrict__ k_cld;
+    const float* __restrict__ ssa;
+    const float* __restrict__ g;
+    const float* __restrict__ albedo;
+    const float* __restrict__ majorant;
+    unsigned long long* abs_dir;
+    unsigned long long* abs_dif;
+    unsigned long long* sfc_dir;
+    unsigned long long* sfc_dif;
+    unsigned long long* sfc_abs;
+    unsigned long long* toa_up;
+    unsigned long long* ledger;
+    unsigned long long* stats;
+    unsigned long long* queue;
+    int nx, ny, nz, bx, by, bz, mx, my, mz;
+    float dx, dy, dz, inv_dx, inv_dy, inv_dz;
+    float cx, cy, cz;  // acceleration-grid cell size in metres
+    float H;
+    float sun_x, sun_y, sun_z;
+    float diffuse_fraction;
+    uint32_t key0, key1;
+    uint32_t rr_below;
+    uint32_t max_iters;
+    int lds_majorant;
+    unsigned long long photons, photon_offset, ncol, col_offset;
+};
+
+enum { L_IN, L_TOA, L_ATM_DIR, L_ATM_DIF, L_SFC, L_RR_GAIN, L_RR_LOSS, L_LOST, L_N };
+enum { S_PHOT, S_COLL, S_NULL, S_GAS, S_CLOUD, S_SFC, S_ESC, S_RR_KILL, S_RR_SURV,
+       S_CROSS, S_ABSORBED, S_CAPPED, S_N };
+
+__device__ __forceinline__ void lds_add(unsigned long long* a, unsigned long long v) {
+    if (v) atomicAdd(a, v);
+}
+
+__device__ __forceinline__ uint64_t lane_mask_lt() {
+    const uint32_t lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
+    extern __shared__ float s_maj[];
+    __shared__ unsigned long long s_ledger[L_N];
+    __shared__ unsigned long long s_stats[S_N];
+
+    if (threadIdx.x < L_N) s_ledger[threadIdx.x] = 0;
+    if (threadIdx.x < S_N) s_stats[threadIdx.x] = 0;
+    const int nmaj = P.mx * P.my * P.mz;
+    if (P.lds_majorant)
+        for (int i = threadIdx.x; i < nmaj; i += blockDim.x) s_maj[i] = P.majorant[i];
+    __syncthreads();
+    const float* __restrict__ maj = P.lds_majorant ? s_maj : P.majorant;
+
+    // ---- per-lane photon state
+    bool alive = false;
+    unsigned long long id = 0;
+    float px = 0.f, py = 0.f, pz = 0.f, ux = 0.f, uy = 0.f, uz = -1.f;
+    int bi = 0, bj = 0, bk = 0;
+    float tau = 0.f;
+    uint32_t w = 0, step = 0, iters = 0;
+    bool direct = false, need_tau = true;
+    uint32_t r1 = 0, r2 = 0, r3 = 0;
+    // merged deposit
+    uint32_t pend_key = kNoCell;
+    unsigned long long pend_amt = 0;
+    // per-photon counters
+    uint32_t n_coll = 0, n_null = 0, n_gas = 0, n_cloud = 0, n_cross = 0;
+    unsigned long long atm_dir = 0, atm_dif = 0;
+
+    // ---- per-wave photon-id pool (wave-uniform)
+    unsigned long long pool_next = 0, pool_end = 0;
+    bool drained = false;
+
+    auto flush_deposit = [&]() {
+        if (pend_key != kNoCell && pend_amt) {
+            const uint32_t cell = pend_key & 0x7fffffffu;
+            if (pend_key & 0x80000000u) {
+                atomicAdd(&P.abs_dif[cell], pend_amt);
+                atm_dif += pend_amt;
+            } else {
+                atomicAdd(&P.abs_dir[cell], pend_amt);
+                atm_dir += pend_amt;
+            }
+        }
+        pend_key = kNoCell;
+        pend_amt = 0;
+    };
+    auto finish_photon = [&]() {
+        alive = false;
+        lds_add(&s_stats[S_COLL], n_coll);
+        lds_add(&s_stats[S_NULL], n_null);
+        lds_add(&s_stats[S_GAS], n_gas);
+        lds_add(&s_stats[S_CLOUD], n_cloud);
+        lds_add(&s_stats[S_CROSS], n_cross);
+        n_coll = n_null = n_gas = n_cloud = n_cross = 0;
+    };
+    auto roulette = [&]() {
+        if (w >= P.rr_below) return;
+        const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 1u), P.key0, P.key1);
+        if ((q.x >> 1) < w) {
+            lds_add(&s_ledger[L_RR_GAIN], kWOne - w);
+            atomicAdd(&s_stats[S_RR_SURV], 1ull);
+            w = kWOne;
+        } else {
+            lds_add(&s_ledger[L_RR_LOSS], w);
+            atomicAdd(&s_stats[S_RR_KILL], 1ull);
+            finish_photon();
+        }
+    };
+
+    for (;;) {
+        // ---- refill finished lanes from the wave's pool of photon ids
+        const uint64_t dead = __ballot(!alive);
+        if (dead && !drained) {
+            const uint32_t need = (uint32_t)__popcll(dead);
+            unsigned long long avail = pool_end - pool_next;
+            unsigned long long base = 0;
+            if (avail < need) {
+                if (__lane_id() == __ffsll((unsigned long long)dead) - 1)
+                    base = atomicAdd(P.queue, (unsigned long long)kPool);
+                base = __shfl(base, __ffsll((unsigned long long)dead) - 1);
+            }
+            if (!alive) {
+                const uint32_t rank = (uint32_t)__popcll(dead & lane_mask_lt());
+                const unsigned long long local = rank < avail ? pool_next + rank : base + (rank - avail);
+                if (local < P.photons) {
+                    // ---- emission at the top of the domain (sec. 2.3)
+                    id = P.photon_offset + local;
+                    const unsigned long long col = (id + P.col_offset) % P.ncol;
+                    const int ic = (int)(col % (unsigned long long)P.nx);
+                    const int jc = (int)(col / (unsigned long long)P.nx);
+                    const uint4 e = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 0u),
+                                           P.key0, P.key1);
+                    px = ((float)ic + u01(e.x)) * P.dx;
+                    py = ((float)jc + u01(e.y)) * P.dy;
+                    pz = P.H;
+                    if (u01(e.z) < P.diffuse_fraction) {
+                        const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 1u),
+                                               P.key0, P.key1);
+                        const float mu = sqrtf(u01_open(q.x));
+                        float sp, cp;
+                        __sincosf(6.28318530717958647f * u01(q.y), &sp, &cp);
+                        const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+                        ux = st * cp;
+                        uy = st * sp;
+                        uz = -mu;
+                        direct = false;
+                    } else {
+                        ux = P.sun_x;
+                        uy = P.sun_y;
+                        uz = P.sun_z;
+                        direct = true;
+                    }
+                    bi = ic / P.bx;
+                    bj = jc / P.by;
+                    bk = P.mz - 1;
+                    w = kWOne;
+                    step = 0;
+                    iters = 0;
+                    need_tau = true;
+                    alive = true;
+                    atomicAdd(&s_stats[S_PHOT], 1ull);
+                    lds_add(&s_ledger[L_IN], kWOne);
+                }
+            }
+            if (avail < need) {
+                pool_next = base + (need - avail);
+                pool_end = base + kPool;
+            } else {
+                pool_next += need;
+            }
+            // ids only grow (pool first, later grabs above pool_end), so once
+            // pool_next passes the photon count no valid id is left
+            drained = pool_next >= P.photons;
+        }
+        if (!__ballot(alive)) break;
+        if (!alive) continue;
+
+        // ---- one pass through the current acceleration-grid cell
+        if (need_tau) {
+            const uint4 r = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 0u), P.key0, P.key1);
+            tau = -__logf(u01_open(r.x));
+            r1 = r.y;
+            r2 = r.z;
+            r3 = r.w;
+            need_tau = false;
+        }
+        if (iters >= P.max_iters) {
+            lds_add(&s_ledger[L_LOST], w);
+            atomicAdd(&s_stats[S_CAPPED], 1ull);
+            finish_photon();
+            continue;
+        }
+        ++iters;
+        const int bidx = (bk * P.my + bj) * P.mx + bi;
+        const float K = maj[bidx];
+        const float x0 = (float)bi * P.cx, y0 = (float)bj * P.cy, z0 = (float)bk * P.cz;
+        float tx = INFINITY, ty = INFINITY, tz = INFINITY;
+        if (ux > 0.f) tx = (x0 + P.cx - px) * rcp(ux);
+        else if (ux < 0.f) tx = (x0 - px) * rcp(ux);
+        if (uy > 0.f) ty = (y0 + P.cy - py) * rcp(uy);
+        else if (uy < 0.f) ty = (y0 - py) * rcp(uy);
+        if (uz > 0.f) tz = (z0 + P.cz - pz) * rcp(uz);
+        else if (uz < 0.f) tz = (z0 - pz) * rcp(uz);
+        tx = fmaxf(tx, 0.f);
+        ty = fmaxf(ty, 0.f);
+        tz = fmaxf(tz, 0.f);
+        int axis = 0;
+        float s_exit = tx;
+        if (ty < s_exit) { s_exit = ty; axis = 1; }
+        if (tz < s_exit) { s_exit = tz; axis = 2; }
+
+        if (K * s_exit >= tau) {
+            // ---- tentative collision inside this cell
+            const float s = tau * rcp(K);
+            px += s * ux;
+            py += s * uy;
+            pz += s * uz;
+            const int i = min(max((int)floorf(px * P.inv_dx), bi * P.bx), bi * P.bx + P.bx - 1);
+            const int j = min(max((int)floorf(py * P.inv_dy), bj * P.by), bj * P.by + P.by - 1);
+            const int k = min(max((int)floorf(pz * P.inv_dz), bk * P.bz), bk * P.bz + P.bz - 1);
+            const uint32_t cell = (uint32_t)((k * P.ny + j) * P.nx + i);
+            const float ke = P.k_ext[cell];
+            const float om = P.ssa[cell];
+            const float ka = ke * (1.0f - om);
+            ++n_coll;
+            if (ka > 0.f) {
+                uint32_t dep = (uint32_t)rintf((float)w * (ka * rcp(K)));
+                dep = min(dep, w);
+                const uint32_t key = cell | (direct ? 0u : 0x80000000u);
+                if (key != pend_key) {
+                    flush_deposit();
+                    pend_key = key;
+                }
+                pend_amt += dep;
+                w -= dep;
+                if (w == 0) {
+                    atomicAdd(&s_stats[S_ABSORBED], 1ull);
+                    finish_photon();
+                    continue;
+                }
+            }
+            const float ks = ke * om;
+            const float den = K - ka;
+            const float ps = den > 0.f ? ks / den : 0.f;
+            const float xi = u01(r1);
+            if (xi < ps) {
+                const float kc = P.k_cld[cell];
+                float mu;
+                if (xi * ke < ps * kc) {
+                    mu = hg_cos(P.g[cell], u01(r2));
+                    ++n_cloud;
+                } else {
+                    mu = rayleigh_cos(u01(r2));
+                    ++n_gas;
+                }
+                turn(ux, uy, uz, mu, u01(r3));
+                direct = false;
+            } else {
+                ++n_null;
+            }
+            roulette();  // counter (id, step, 1): same free-path index
+            ++step;
+            need_tau = true;
+            continue;
+        }
+
+        // ---- cross into the next acceleration-grid cell
+        tau -= K * s_exit;
+        px += s_exit * ux;
+        py += s_exit * uy;
+        pz += s_exit * uz;
+        if (axis == 2) {
+            if (uz < 0.f && bk == 0) {
+                // ---- Lambertian surface (sec. 2.3)
+                pz = 0.f;
+                const int i = min(max((int)floorf(px * P.inv_dx), bi * P.bx), bi * P.bx + P.bx - 1);
+                const int j = min(max((int)floorf(py * P.inv_dy), bj * P.by), bj * P.by + P.by - 1);
+                const int c2 = j * P.nx + i;
+                atomicAdd(direct ? &P.sfc_dir[c2] : &P.sfc_dif[c2], (unsigned long long)w);
+                const uint32_t wn = min(w, (uint32_t)rintf(P.albedo[c2] * (float)w));
+                if (w != wn) {
+                    atomicAdd(&P.sfc_abs[c2], (unsigned long long)(w - wn));
+                    lds_add(&s_ledger[L_SFC], w - wn);
+                }
+                atomicAdd(&s_stats[S_SFC], 1ull);
+                w = wn;
+                if (w == 0) {
+                    atomicAdd(&s_stats[S_ABSORBED], 1ull);
+                    finish_photon();
+                    continue;
+                }
+                const float mu = sqrtf(u01_open(r2));
+                float sp, cp;
+                __sincosf(6.28318530717958647f * u01(r3), &sp, &cp);
+                const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+                ux = st * cp;
+                uy = st * sp;
+                uz = mu;
+                direct = false;
+                roulette();
+                ++step;
+                need_tau = true;
+                continue;
+            }
+            if (uz > 0.f && bk == P.mz - 1) {
+                // ---- leaves through the top of the domain
+                const int i = min(max((int)floorf(px * P.inv_dx), bi * P.bx), bi * P.bx + P.bx - 1);
+                const int j = min(max((int)floorf(py * P.inv_dy), bj * P.by), bj * P.by + P.by - 1);
+                atomicAdd(&P.toa_up[j * P.nx + i], (unsigned long long)w);
+                lds_add(&s_ledger[L_TOA], w);
+                atomicAdd(&s_stats[S_ESC], 1ull);
+                finish_photon();
+                continue;
+            }
+            if (uz > 0.f) {
+                ++bk;
+                pz = (float)bk * P.cz;
+            } else {
+                --bk;
+                pz = (float)(bk + 1) * P.cz;
+            }
+        } else if (axis == 0) {
+            if (ux > 0.f) {
+                bi = bi + 1 == P.mx ? 0 : bi + 1;
+                px = (float)bi * P.cx;
+            } else {
+                bi = bi == 0 ? P.mx - 1 : bi - 1;
+                px = (float)(bi + 1) * P.cx;
+            }
+        } else {
+            if (uy > 0.f) {
+                bj = bj + 1 == P.my ? 0 : bj + 1;
+                py = (float)bj * P.cy;
+            } else {
+                bj = bj == 0 ? P.my - 1 : bj - 1;
+                py = (float)(bj + 1) * P.cy;
+            }
+        }
+        ++n_cross;
+    }
+
+    flush_deposit();
+    lds_add(&s_ledger[L_ATM_DIR], atm_dir);
+    lds_add(&s_ledger[L_ATM_DIF], atm_dif);
+    __syncthreads();
+    if (threadIdx.x < L_N && s_ledger[threadIdx.x]) atomicAdd(&P.ledger[threadIdx.x], s_ledger[threadIdx.x]);
+    if (threadIdx.x < S_N && s_stats[threadIdx.x]) atomicAdd(&P.stats[threadIdx.x], s_stats[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+__global__ void fill_u64_kernel(unsigned long long* p, size_t n, unsigned long long v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Row pass of the majorant build: thread (bi, j, k) takes the maximum of
+// the bx cells of row (j, k) inside acceleration cell column bi and merges it
+// into the acceleration cell with an integer max of the FP32 bits (exact,
+// as every value is >= +0; non-positive values and NaN count as 0).
+__global__ void majorant_kernel(const float* __restrict__ k_ext, uint32_t* __restrict__ maj, int nx, int ny,
+                                int nz, int bx, int by, int bz) {
+    const int mx = nx / bx, my = ny / by;
+    const size_t n = (size_t)mx * ny * nz;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int bi = (int)(t % mx);
+        const size_t row = t / mx;  // j + ny * k
+        const int j = (int)(row % ny);
+        const int k = (int)(row / ny);
+        const float* src = k_ext + row * nx + (size_t)bi * bx;
+        uint32_t m = 0;
+        for (int q = 0; q < bx; ++q) {
+            const float v = src[q];
+            const uint32_t bits = v > 0.0f ? __float_as_uint(v) : 0u;
+            m = bits > m ? bits : m;
+        }
+        atomicMax(&maj[((size_t)(k / bz) * my + j / by) * mx + bi], m);
+    }
+}
+
+// Validation of the inputs: sets bit 0 of *flag for any violation.
+__global__ void validate_kernel(const float* __restrict__ ke, const float* __restrict__ kc,
+                                const float* __restrict__ om, const float* __restrict__ g,
+                                const float* __restrict__ alb, size_t ncell, size_t ncol, uint32_t* flag) {
+    uint32_t bad = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
+        const float a = ke[i], b = kc[i], c = om[i], d = g[i];
+        const bool ok = (a >= 0.f) && (a < INFINITY) && (b >= 0.f) && (b <= a) && (c >= 0.f) && (c <= 1.f) &&
+                        (d >= -1.f) && (d <= 1.f);
+        bad |= ok ? 0u : 1u;
+    }
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ncol; i += (size_t)gridDim.x * blockDim.x) {
+        const float a = alb[i];
+        bad |= (a >= 0.f && a <= 1.f) ? 0u : 1u;
+    }
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
+__global__ void finalize3_kernel(const unsigned long long* __restrict__ raw, float* __restrict__ out, size_t plane,
+                                 size_t n, double norm, const double* __restrict__ layer_scale) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double s = layer_scale ? layer_scale[i / plane] * norm : norm;
+        out[i] = (float)((double)raw[i] * s);
+    }
+}
+
+__global__ void philox_kernel(const uint4* __restrict__ ctr, uint32_t k0, uint32_t k1, uint4* __restrict__ out,
+                              uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox(ctr[i], k0, k1);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+thread_local char g_err[256] = "";
+thread_local hipEvent_t g_t0 = nullptr, g_t1 = nullptr;
+thread_local bool g_timed = false;
+
+rt3d_status dev_fail(hipError_t e, const char* where) {
+    snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+    return RT3D_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return dev_fail(e_, #expr); \
+    } while (0)
+
+struct Shape {
+    int nx, ny, nz, bx, by, bz, mx, my, mz;
+    size_t ncell, ncol, nmaj;
+};
+
+bool grid_ok(const rt3d_grid* g) {
+    if (!g || g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return false;
+    if (!(g->dx > 0.f) || !(g->dy > 0.f) || !(g->dz > 0.f)) return false;
+    if (!std::isfinite(g->dx) || !std::isfinite(g->dy) || !std::isfinite(g->dz)) return false;
+    const long long n = (long long)g->nx * g->ny * g->nz;
+    return n < 0x7fffffffLL;
+}
+
+void resolve_options(const rt3d_grid* g, const rt3d_options* in, rt3d_options* out) {
+    rt3d_default_options(out);
+    if (in) *out = *in;
+    if (out->brick_x <= 0) out->brick_x = g->nx % 8 == 0 ? 8 : 1;
+    if (out->brick_y <= 0) out->brick_y = g->ny % 8 == 0 ? 8 : 1;
+    if (out->brick_z <= 0) out->brick_z = g->nz % 8 == 0 ? 8 : 1;
+    if (out->max_iters == 0) out->max_iters = 1u << 24;
+}
+
+bool shape_of(const rt3d_grid* g, const rt3d_options* o, Shape* s) {
+    if (!grid_ok(g)) return false;
+    if (o->brick_x <= 0 || o->brick_y <= 0 || o->brick_z <= 0) return false;
+    if (g->nx % o->brick_x || g->ny % o->brick_y || g->nz % o->brick_z) return false;
+    s->nx = g->nx; s->ny = g->ny; s->nz = g->nz;
+    s->bx = o->brick_x; s->by = o->brick_y; s->bz = o->brick_z;
+    s->mx = g->nx / o->brick_x; s->my = g->ny / o->brick_y; s->mz = g->nz / o->brick_z;
+    s->ncell = (size_t)g->nx * g->ny * g->nz;
+    s->ncol = (size_t)g->nx * g->ny;
+    s->nmaj = (size_t)s->mx * s->my * s->mz;
+    return true;
+}
+
+constexpr size_t kCtrlBytes = 256;  // queue counter + validation flag
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+unsigned grid_for(size_t n, unsigned block = 256, unsigned cap = 8192) {
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+rt3d_status zero_u64(unsigned long long* p, size_t n, hipStream_t st) {
+    if (!n) return RT3D_OK;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, 0ull);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int rt3d_abi_version(void) { return RT3D_ABI_VERSION; }
+
+const char* rt3d_status_string(rt3d_status s) {
+    switch (s) {
+        case RT3D_OK: return "ok";
+        case RT3D_EINVAL: return "invalid argument";
+        case RT3D_EDOMAIN: return "field value out of range";
+        case RT3D_EDEVICE: return "HIP device error";
+    }
+    return "unknown status";
+}
+
+const char* rt3d_last_device_error(void) { return g_err; }
+
+void rt3d_default_options(rt3d_options* opt) {
+    if (!opt) return;
+    memset(opt, 0, sizeof *opt);
+    opt->diffuse_fraction = 0.0f;
+    opt->rr_threshold = 0.5f;
+    opt->max_iters = 1u << 24;
+}
+
+size_t rt3d_workspace_size(const rt3d_grid* grid, const rt3d_options* opt) {
+    rt3d_options o;
+    if (!grid_ok(grid)) return 0;
+    resolve_options(grid, opt, &o);
+    Shape s;
+    if (!shape_of(grid, &o, &s)) return 0;
+    return kCtrlBytes + align256(s.nmaj * sizeof(float));
+}
+
+rt3d_status rt3d_majorant_build(const rt3d_grid* grid, const float* k_ext, int32_t bx, int32_t by, int32_t bz,
+                                float* majorant, void* stream) {
+    rt3d_options o;
+    rt3d_default_options(&o);
+    o.brick_x = bx; o.brick_y = by; o.brick_z = bz;
+    Shape s;
+    if (!k_ext || !majorant || bx <= 0 || by <= 0 || bz <= 0 || !shape_of(grid, &o, &s)) return RT3D_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(s.nmaj)), dim3(256), 0, st, (uint32_t*)majorant, s.nmaj, 0u);
+    HIP_TRY(hipGetLastError());
+    const size_t n = (size_t)s.mx * s.ny * s.nz;
+    hipLaunchKernelGGL(majorant_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, k_ext,
+                       (uint32_t*)majorant, s.nx, s.ny, s.nz, s.bx, s.by, s.bz);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, const float* surface_albedo,
+                       double sza_deg, double azimuth_deg, uint64_t photons, uint64_t seed,
+                       const rt3d_options* opt, const rt3d_tallies* out, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+    g_timed = false;
+    rt3d_options o;
+    if (!grid_ok(grid)) return RT3D_EINVAL;
+    resolve_options(grid, opt, &o);
+    Shape s;
+    if (!shape_of(grid, &o, &s)) return RT3D_EINVAL;
+    if (!props || !props->k_ext || !props->k_ext_cloud || !props->ssa || !props->g || !surface_albedo)
+        return RT3D_EINVAL;
+    if (!out || !out->abs_dir || !out->abs_dif || !out->sfc_dir || !out->sfc_dif || !out->sfc_abs ||
+        !out->toa_up || !out->ledger || !out->stats)
+        return RT3D_EINVAL;
+    if (!(sza_deg >= 0.0 && sza_deg < 90.0) || !std::isfinite(azimuth_deg) || photons == 0) return RT3D_EINVAL;
+    if (!(o.diffuse_fraction >= 0.f && o.diffuse_fraction <= 1.f)) return RT3D_EINVAL;
+    if (!(o.rr_threshold >= 0.f && o.rr_threshold <= 1.f)) return RT3D_EINVAL;
+    if (o.photon_offset + photons < o.photon_offset) return RT3D_EINVAL;
+    const size_t need = rt3d_workspace_size(grid, &o);
+    if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) return RT3D_EINVAL;
+    if (o.grid_blocks < 0 || o.block_threads < 0) return RT3D_EINVAL;
+    if (o.block_threads && o.block_threads != kBlock) return RT3D_EINVAL;
+
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    unsigned long long* queue = (unsigned long long*)ws;
+    uint32_t* flag = (uint32_t*)(ws + 128);
+    float* maj = (float*)(ws + kCtrlBytes);
+
+    // control block: queue counter and validation flag
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(32), 0, st, (unsigned long long*)ws, kCtrlBytes / 8, 0ull);
+    HIP_TRY(hipGetLastError());
+
+    if (o.flags & RT3D_FLAG_VALIDATE) {
+        hipLaunchKernelGGL(validate_kernel, dim3(grid_for(s.ncell, 256, 4096)), dim3(256), 0, st, props->k_ext,
+                           props->k_ext_cloud, props->ssa, props->g, surface_albedo, s.ncell, s.ncol, flag);
+        HIP_TRY(hipGetLastError());
+        uint32_t h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h) return RT3D_EDOMAIN;
+    }
+
+    if (!(o.flags & RT3D_FLAG_ACCUMULATE)) {
+        rt3d_status z;
+        if ((z = zero_u64((unsigned long long*)out->abs_dir, s.ncell, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->abs_dif, s.ncell, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->sfc_dir, s.ncol, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->sfc_dif, s.ncol, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->sfc_abs, s.ncol, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->toa_up, s.ncol, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->ledger, RT3D_LEDGER_N, st)) != RT3D_OK) return z;
+        if ((z = zero_u64((unsigned long long*)out->stats, RT3D_STATS_N, st)) != RT3D_OK) return z;
+    }
+
+    rt3d_status ms = rt3d_majorant_build(grid, props->k_ext, s.bx, s.by, s.bz, maj, stream);
+    if (ms != RT3D_OK) return ms;
+
+    TraceParams P;
+    memset(&P, 0, sizeof P);
+    P.k_ext = props->k_ext;
+    P.k_cld = props->k_ext_cloud;
+    P.ssa = props->ssa;
+    P.g = props->g;
+    P.albedo = surface_albedo;
+    P.majorant = maj;
+    P.abs_dir = (unsigned long long*)out->abs_dir;
+    P.abs_dif = (unsigned long long*)out->abs_dif;
+    P.sfc_dir = (unsigned long long*)out->sfc_dir;
+    P.sfc_dif = (unsigned long long*)out->sfc_dif;
+    P.sfc_abs = (unsigned long long*)out->sfc_abs;
+    P.toa_up = (unsigned long long*)out->toa_up;
+    P.ledger = (unsigned long long*)out->ledger;
+    P.stats = (unsigned long long*)out->stats;
+    P.queue = queue;
+    P.nx = s.nx; P.ny = s.ny; P.nz = s.nz;
+    P.bx = s.bx; P.by = s.by; P.bz = s.bz;
+    P.mx = s.mx; P.my = s.my; P.mz = s.mz;
+    P.dx = grid->dx; P.dy = grid->dy; P.dz = grid->dz;
+    P.inv_dx = 1.0f / grid->dx; P.inv_dy = 1.0f / grid->dy; P.inv_dz = 1.0f / grid->dz;
+    P.cx = (float)s.bx * grid->dx; P.cy = (float)s.by * grid->dy; P.cz = (float)s.bz * grid->dz;
+    P.H = (float)s.nz * grid->dz;
+    const double th = sza_deg * M_PI / 180.0, ph = azimuth_deg * M_PI / 180.0;
+    P.sun_x = (float)(-sin(th) * sin(ph));
+    P.sun_y = (float)(-sin(th) * cos(ph));
+    P.sun_z = (float)(-cos(th));
+    P.diffuse_fraction = o.diffuse_fraction;
+    P.key0 = (uint32_t)seed;
+    P.key1 = (uint32_t)(seed >> 32);
+    P.rr_below = (uint32_t)std::nearbyint((double)o.rr_threshold * 2147483648.0);
+    P.max_iters = o.max_iters;
+    P.photons = photons;
+    P.photon_offset = o.photon_offset;
+    P.ncol = s.ncol;
+    // run offset of the systematic column sampling: counter (0, 0, 0xfffffffe, 0), word 0
+    {
+        uint32_t c[4] = {0u, 0u, 0xfffffffeu, 0u};
+        uint32_t k0 = P.key0, k1 = P.key1;
+        for (int r = 0; r < 10; ++r) {
+            if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+            const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+            const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+            c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
+        }
+        P.col_offset = ((unsigned long long)c[0] * (unsigned long long)s.ncol) >> 32;
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t maj_bytes = s.nmaj * sizeof(float);
+    const size_t lds_limit = o.lds_majorant > 0 ? (size_t)max_lds - 1024 : kLdsMajorantBytes;
+    P.lds_majorant = (o.lds_majorant >= 0 && maj_bytes <= lds_limit && maj_bytes + 1024 <= (size_t)max_lds) ? 1 : 0;
+    const size_t lds = P.lds_majorant ? maj_bytes : 0;
+
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel, kBlock, lds));
+    if (per_cu < 1) per_cu = 1;
+    unsigned blocks = o.grid_blocks ? (unsigned)o.grid_blocks : (unsigned)(ncu * per_cu);
+    // never more lanes than photons need
+    const unsigned long long max_blocks = (photons + kBlock - 1) / kBlock;
+    if (blocks > max_blocks) blocks = (unsigned)max_blocks;
+    if (blocks < 1) blocks = 1;
+
+    if (o.flags & RT3D_FLAG_TIME) {
+        if (!g_t0) HIP_TRY(hipEventCreate(&g_t0));
+        if (!g_t1) HIP_TRY(hipEventCreate(&g_t1));
+        HIP_TRY(hipEventRecord(g_t0, st));
+    }
+    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), lds, st, P);
+    HIP_TRY(hipGetLastError());
+    if (o.flags & RT3D_FLAG_TIME) {
+        HIP_TRY(hipEventRecord(g_t1, st));
+        g_timed = true;
+    }
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_last_trace_ms(float* ms) {
+    if (!ms || !g_timed) return RT3D_EINVAL;
+    HIP_TRY(hipEventSynchronize(g_t1));
+    HIP_TRY(hipEventElapsedTime(ms, g_t0, g_t1));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_finalize(const rt3d_grid* grid, const rt3d_tallies* raw, uint64_t photons,
+                          const double* layer_scale, double flux_scale, float* abs_dir, float* abs_dif,
+                          float* sfc_dir, float* sfc_dif, float* sfc_abs, float* toa_up, void* stream) {
+    if (!grid_ok(grid) || !raw || photons == 0 || !std::isfinite(flux_scale)) return RT3D_EINVAL;
+    const size_t ncell = (size_t)grid->nx * grid->ny * grid->nz, ncol = (size_t)grid->nx * grid->ny;
+    const double norm = (double)ncol / ((double)photons * 2147483648.0);
+    hipStream_t st = (hipStream_t)stream;
+    struct Item { const uint64_t* src; float* dst; size_t n; bool three; };
+    const Item items[6] = {{raw->abs_dir, abs_dir, ncell, true}, {raw->abs_dif, abs_dif, ncell, true},
+                           {raw->sfc_dir, sfc_dir, ncol, false}, {raw->sfc_dif, sfc_dif, ncol, false},
+                           {raw->sfc_abs, sfc_abs, ncol, false}, {raw->toa_up, toa_up, ncol, false}};
+    for (const Item& it : items) {
+        if (!it.dst) continue;
+        if (!it.src) return RT3D_EINVAL;
+        hipLaunchKernelGGL(finalize3_kernel, dim3(grid_for(it.n, 256, 8192)), dim3(256), 0, st,
+                           (const unsigned long long*)it.src, it.dst, it.three ? ncol : it.n, it.n,
+                           it.three ? norm : norm * flux_scale, it.three ? layer_scale : nullptr);
+        HIP_TRY(hipGetLastError());
+    }
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_philox4x32_10(const uint32_t* ctr, uint64_t seed, uint32_t* out, uint32_t n, void* stream) {
+    if (!ctr || !out) return RT3D_EINVAL;
+    if (n == 0) return RT3D_OK;
+    hipLaunchKernelGGL(philox_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       (const uint4*)ctr, (uint32_t)seed, (uint32_t)(seed >> 32), (uint4*)out, n);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+}  // extern "C"

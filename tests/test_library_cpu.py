@@ -1,0 +1,106 @@
+"""CPU-side checks of the HIP library boundary: the shared library loads,
+exports every entry point include/rt3d.h declares, and its host-only entry
+points (options, workspace size, argument checks) behave as documented.
+No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt3d.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt3d_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2208_05247_amd import rt3d
+    if not os.path.exists(rt3d.LIB_PATH):
+        pytest.fail("librt3d.so is not built (run __graft_entry__.build())")
+    return rt3d.load()
+
+
+def test_exports_match_header(lib):
+    from paper_2208_05247_amd import rt3d
+    decl = declared_functions()
+    assert decl, "no declarations found"
+    out = subprocess.check_output(["nm", "-D", "--defined-only", rt3d.LIB_PATH], text=True)
+    exported = set(re.findall(r"\bT (rt3d_[a-z0-9_]+)", out))
+    missing = [f for f in decl if f not in exported]
+    assert not missing, missing
+    for f in decl:
+        assert hasattr(lib, f)
+    assert set(rt3d.EXPORTS) <= set(decl)
+
+
+def test_abi_and_strings(lib):
+    assert lib.rt3d_abi_version() == 1
+    for s in range(4):
+        assert lib.rt3d_status_string(s)
+    assert lib.rt3d_status_string(99) == b"unknown status"
+
+
+def test_default_options(lib):
+    from paper_2208_05247_amd import rt3d
+    o = rt3d.Options()
+    lib.rt3d_default_options(ctypes.byref(o))
+    assert abs(o.rr_threshold - 0.5) < 1e-7
+    assert o.diffuse_fraction == 0.0 and o.flags == 0 and o.max_iters == 1 << 24
+    assert o.photon_offset == 0 and o.grid_blocks == 0
+
+
+def test_workspace_size_host_only(lib):
+    from paper_2208_05247_amd import rt3d
+    from paper_2208_05247_amd.synthetic import Grid
+    g = Grid(256, 256, 128, 50.0, 50.0, 25.0)
+    o = rt3d.options(brick=(8, 8, 8))
+    n = rt3d.workspace_size(g, o)
+    assert n == 256 + 32 * 32 * 16 * 4
+    bad = rt3d.options(brick=(3, 8, 8))
+    with pytest.raises(rt3d.Rt3dError):
+        rt3d.workspace_size(g, bad)
+    assert lib.rt3d_workspace_size(None, None) == 0
+    z = rt3d.Grid(0, 4, 4, 1.0, 1.0, 1.0)
+    assert lib.rt3d_workspace_size(ctypes.byref(z), None) == 0
+
+
+def test_einval_before_any_launch(lib):
+    """Argument errors are reported from host checks (null pointers, bad
+    sizes); nothing reaches the device."""
+    from paper_2208_05247_amd import rt3d
+    g = rt3d.Grid(8, 8, 8, 10.0, 10.0, 10.0)
+    props = rt3d.OpticalProps(0, 0, 0, 0)
+    t = rt3d.TalliesStruct(*([0] * 8))
+    o = rt3d.options(brick=(4, 4, 4))
+    st = lib.rt3d_trace(ctypes.byref(g), ctypes.byref(props), None, 30.0, 0.0, 100, 1,
+                        ctypes.byref(o), ctypes.byref(t), None, 0, None)
+    assert st == rt3d.EINVAL
+    st = lib.rt3d_trace(None, None, None, 30.0, 0.0, 100, 1, None, None, None, 0, None)
+    assert st == rt3d.EINVAL
+    assert lib.rt3d_majorant_build(ctypes.byref(g), None, 4, 4, 4, None, None) == rt3d.EINVAL
+    assert lib.rt3d_finalize(None, None, 1, None, 1.0, None, None, None, None, None, None, None) == rt3d.EINVAL
+    assert lib.rt3d_philox4x32_10(None, 1, None, 4, None) == rt3d.EINVAL
+    ms = ctypes.c_float()
+    assert lib.rt3d_last_trace_ms(ctypes.byref(ms)) == rt3d.EINVAL
+
+
+def test_product_path_has_no_fallback():
+    """The binding imports nothing from the oracle and refuses to run
+    without the HIP library."""
+    src = open(os.path.join(ROOT, "paper_2208_05247_amd", "rt3d.py")).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+    from paper_2208_05247_amd import rt3d
+    with pytest.raises(RuntimeError):
+        saved = rt3d._lib
+        rt3d._lib = None
+        try:
+            rt3d.load(os.path.join(ROOT, "does_not_exist.so"))
+        finally:
+            rt3d._lib = saved

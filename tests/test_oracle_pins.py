@@ -374,9 +374,9 @@ def test_analog_brute_force_tiny_grid(case):
         f = syn.random_fields(grid, seed=10, k_max=0.03, albedo_range=(0.1, 0.9))
         sza, az, fd, brick = 35.0, 70.0, 0.0, (2, 2, 2)
     else:
-        grid = syn.Grid(3, 1, 5, 50.0, 80.0, 30.0)
+        grid = syn.Grid(3, 2, 5, 50.0, 80.0, 30.0)
         f = syn.random_fields(grid, seed=11, k_max=0.04, albedo_range=(0.0, 0.5))
-        sza, az, fd, brick = 55.0, 250.0, 0.3, (3, 1, 5)
+        sza, az, fd, brick = 55.0, 250.0, 0.3, (3, 2, 5)
     B = 32
     rng = np.random.default_rng(100 + case)
     per = 6000

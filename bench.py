@@ -36,6 +36,25 @@ def algorithmic_bytes(stats) -> float:
             + 20.0 * s["surface"] + 8.0 * s["escape"])
 
 
+def measured_traffic(brick, photons):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on this exact kernel source and workload; else None."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2208_05247_amd", "csrc", "rt3d.hip")
+    prof = os.path.join(ROOT, "profiles", "trace_kernel_les_cumulus_256x256x128.md")
+    if tuple(brick) != (8, 8, 8) or photons != 1 << 26 or not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    fields = {}
+    for line in open(prof):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256_16") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(wl, target_s: float = 12.0) -> dict:
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -66,7 +85,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lds-majorant", type=int, default=0)
     ap.add_argument("--brick", type=int, default=8)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only run one plain device copy of this many bytes (for HBM counter scaling)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tracer is single-GPU (photons or g-points would be "
               "sharded across GPUs with one all-reduce of the tallies; not built here)", file=sys.stderr)
@@ -111,6 +141,7 @@ def main():
     mean_kms = sum(kernel_ms) / len(kernel_ms)
     bytes_per_launch = algorithmic_bytes(tot) / args.steps
     achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
+    traffic = measured_traffic(wl.brick, wl.photons) if args.lds_majorant == 0 else None
     res = {
         "metric": METRIC,
         "value": events / wall,
@@ -132,7 +163,8 @@ def main():
         "events_per_photon": events / max(1, tot["photons"]),
         "trace_kernel_ms": mean_kms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_GBps": None if traffic is None else traffic / (mean_kms * 1e-3) / 1e9,
                      "kernel": "trace_kernel",
                      "bytes_per_launch": bytes_per_launch},
         "paper_context": "A100 40GiB: ~1.9e8 photons/s derived from 90 s for 112 g-points x 256 "

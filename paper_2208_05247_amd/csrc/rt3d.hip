@@ -34,10 +34,10 @@
 namespace {
 
 constexpr uint32_t kWOne = 0x80000000u;  // weight one in units of 2^-31
-constexpr int kBlock = 256;              // threads per workgroup
+constexpr int kBlock = 1024;             // threads per workgroup
 constexpr uint32_t kPool = 256;          // photon ids fetched per wave refill
 constexpr uint32_t kNoCell = 0xffffffffu;
-constexpr size_t kLdsMajorantBytes = 16 * 1024;  // automatic LDS staging limit
+constexpr size_t kLdsMajorantBytes = 64 * 1024;  // automatic LDS staging limit
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): per round the counter becomes
@@ -105,10 +105,7 @@ __device__ __forceinline__ void turn(float& x, float& y, float& z, float mu, flo
 }
 
 struct TraceParams {
-    const float* __restrict__ k_ext;
-    const float* __restrict__ k_cld;
-    const float* __restrict__ ssa;
-    const float* __restrict__ g;
+    const float4* __restrict__ cells;  // packed (k_ext, ssa, k_ext_cloud, g) per cell
     const float* __restrict__ albedo;
     const float* __restrict__ majorant;
     unsigned long long* abs_dir;
@@ -129,7 +126,6 @@ struct TraceParams {
     uint32_t key0, key1;
     uint32_t rr_below;
     uint32_t max_iters;
-    int lds_majorant;
     unsigned long long photons, photon_offset, ncol, col_offset;
 };
 
@@ -146,32 +142,39 @@ __device__ __forceinline__ uint64_t lane_mask_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-__global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
+enum Outcome { kCollision = 0, kSurface = 1, kEscape = 2, kCapped = 3 };
+
+// One workgroup = kBlock lanes, one photon per lane.  Each loop iteration of
+// a lane: (re)fill the lane with a new photon if it has none, draw the free
+// path's four random words, walk acceleration-grid cells until the tentative
+// collision / surface / top, then handle that event.  kLds selects the
+// majorant grid in LDS (staged once per workgroup) or read through L1/L2.
+template <bool kLds>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) trace_kernel(const TraceParams P) {
     extern __shared__ float s_maj[];
     __shared__ unsigned long long s_ledger[L_N];
     __shared__ unsigned long long s_stats[S_N];
 
     if (threadIdx.x < L_N) s_ledger[threadIdx.x] = 0;
     if (threadIdx.x < S_N) s_stats[threadIdx.x] = 0;
-    const int nmaj = P.mx * P.my * P.mz;
-    if (P.lds_majorant)
+    if (kLds) {
+        const int nmaj = P.mx * P.my * P.mz;
         for (int i = threadIdx.x; i < nmaj; i += blockDim.x) s_maj[i] = P.majorant[i];
+    }
     __syncthreads();
-    const float* __restrict__ maj = P.lds_majorant ? s_maj : P.majorant;
+    const float* __restrict__ maj = kLds ? s_maj : P.majorant;
 
     // ---- per-lane photon state
     bool alive = false;
     unsigned long long id = 0;
     float px = 0.f, py = 0.f, pz = 0.f, ux = 0.f, uy = 0.f, uz = -1.f;
     int bi = 0, bj = 0, bk = 0;
-    float tau = 0.f;
     uint32_t w = 0, step = 0, iters = 0;
-    bool direct = false, need_tau = true;
-    uint32_t r1 = 0, r2 = 0, r3 = 0;
-    // merged deposit
+    bool direct = false;
+    // merged deposit: cell index, bit 31 set for diffuse
     uint32_t pend_key = kNoCell;
     unsigned long long pend_amt = 0;
-    // per-photon counters
+    // per-photon counters (folded into LDS when the photon ends)
     uint32_t n_coll = 0, n_null = 0, n_gas = 0, n_cloud = 0, n_cross = 0;
     unsigned long long atm_dir = 0, atm_dif = 0;
 
@@ -180,7 +183,7 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
     bool drained = false;
 
     auto flush_deposit = [&]() {
-        if (pend_key != kNoCell && pend_amt) {
+        if (pend_amt) {
             const uint32_t cell = pend_key & 0x7fffffffu;
             if (pend_key & 0x80000000u) {
                 atomicAdd(&P.abs_dif[cell], pend_amt);
@@ -202,6 +205,8 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
         lds_add(&s_stats[S_CROSS], n_cross);
         n_coll = n_null = n_gas = n_cloud = n_cross = 0;
     };
+    // Russian roulette (sec. 2.3) with the current free path's counter
+    // (id, step, 1): survive with probability w, then weight one.
     auto roulette = [&]() {
         if (w >= P.rr_below) return;
         const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 1u), P.key0, P.key1);
@@ -215,18 +220,21 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
             finish_photon();
         }
     };
+    auto cell_ix = [&](float v, float inv, int b, int n) {
+        return min(max((int)floorf(v * inv), b * n), b * n + n - 1);
+    };
 
     for (;;) {
         // ---- refill finished lanes from the wave's pool of photon ids
         const uint64_t dead = __ballot(!alive);
         if (dead && !drained) {
             const uint32_t need = (uint32_t)__popcll(dead);
-            unsigned long long avail = pool_end - pool_next;
+            const int leader = __ffsll((unsigned long long)dead) - 1;
+            const unsigned long long avail = pool_end - pool_next;
             unsigned long long base = 0;
             if (avail < need) {
-                if (__lane_id() == __ffsll((unsigned long long)dead) - 1)
-                    base = atomicAdd(P.queue, (unsigned long long)kPool);
-                base = __shfl(base, __ffsll((unsigned long long)dead) - 1);
+                if ((int)__lane_id() == leader) base = atomicAdd(P.queue, (unsigned long long)kPool);
+                base = __shfl(base, leader);
             }
             if (!alive) {
                 const uint32_t rank = (uint32_t)__popcll(dead & lane_mask_lt());
@@ -235,8 +243,8 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
                     // ---- emission at the top of the domain (sec. 2.3)
                     id = P.photon_offset + local;
                     const unsigned long long col = (id + P.col_offset) % P.ncol;
-                    const int ic = (int)(col % (unsigned long long)P.nx);
-                    const int jc = (int)(col / (unsigned long long)P.nx);
+                    const int ic = (int)(col % (unsigned)P.nx);
+                    const int jc = (int)(col / (unsigned)P.nx);
                     const uint4 e = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 0u),
                                            P.key0, P.key1);
                     px = ((float)ic + u01(e.x)) * P.dx;
@@ -265,7 +273,6 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
                     w = kWOne;
                     step = 0;
                     iters = 0;
-                    need_tau = true;
                     alive = true;
                     atomicAdd(&s_stats[S_PHOT], 1ull);
                     lds_add(&s_ledger[L_IN], kWOne);
@@ -284,57 +291,87 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
         if (!__ballot(alive)) break;
         if (!alive) continue;
 
-        // ---- one pass through the current acceleration-grid cell
-        if (need_tau) {
-            const uint4 r = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 0u), P.key0, P.key1);
-            tau = -__logf(u01_open(r.x));
-            r1 = r.y;
-            r2 = r.z;
-            r3 = r.w;
-            need_tau = false;
-        }
-        if (iters >= P.max_iters) {
-            lds_add(&s_ledger[L_LOST], w);
-            atomicAdd(&s_stats[S_CAPPED], 1ull);
-            finish_photon();
-            continue;
-        }
-        ++iters;
-        const int bidx = (bk * P.my + bj) * P.mx + bi;
-        const float K = maj[bidx];
-        const float x0 = (float)bi * P.cx, y0 = (float)bj * P.cy, z0 = (float)bk * P.cz;
-        float tx = INFINITY, ty = INFINITY, tz = INFINITY;
-        if (ux > 0.f) tx = (x0 + P.cx - px) * rcp(ux);
-        else if (ux < 0.f) tx = (x0 - px) * rcp(ux);
-        if (uy > 0.f) ty = (y0 + P.cy - py) * rcp(uy);
-        else if (uy < 0.f) ty = (y0 - py) * rcp(uy);
-        if (uz > 0.f) tz = (z0 + P.cz - pz) * rcp(uz);
-        else if (uz < 0.f) tz = (z0 - pz) * rcp(uz);
-        tx = fmaxf(tx, 0.f);
-        ty = fmaxf(ty, 0.f);
-        tz = fmaxf(tz, 0.f);
-        int axis = 0;
-        float s_exit = tx;
-        if (ty < s_exit) { s_exit = ty; axis = 1; }
-        if (tz < s_exit) { s_exit = tz; axis = 2; }
+        // ---- random words of this free path: tau, event, cos(theta), phi
+        const uint4 r = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 0u), P.key0, P.key1);
+        float tau = -__logf(u01_open(r.x));
 
-        if (K * s_exit >= tau) {
-            // ---- tentative collision inside this cell
-            const float s = tau * rcp(K);
-            px += s * ux;
-            py += s * uy;
-            pz += s * uz;
-            const int i = min(max((int)floorf(px * P.inv_dx), bi * P.bx), bi * P.bx + P.bx - 1);
-            const int j = min(max((int)floorf(py * P.inv_dy), bj * P.by), bj * P.by + P.by - 1);
-            const int k = min(max((int)floorf(pz * P.inv_dz), bk * P.bz), bk * P.bz + P.bz - 1);
+        // ---- walk acceleration-grid cells until the path ends
+        int outcome;
+        float K;
+        for (;;) {
+            if (iters >= P.max_iters) { outcome = kCapped; break; }
+            ++iters;
+            K = maj[(bk * P.my + bj) * P.mx + bi];
+            const float x0 = (float)bi * P.cx, y0 = (float)bj * P.cy, z0 = (float)bk * P.cz;
+            float tx = INFINITY, ty = INFINITY, tz = INFINITY;
+            if (ux > 0.f) tx = (x0 + P.cx - px) * rcp(ux);
+            else if (ux < 0.f) tx = (x0 - px) * rcp(ux);
+            if (uy > 0.f) ty = (y0 + P.cy - py) * rcp(uy);
+            else if (uy < 0.f) ty = (y0 - py) * rcp(uy);
+            if (uz > 0.f) tz = (z0 + P.cz - pz) * rcp(uz);
+            else if (uz < 0.f) tz = (z0 - pz) * rcp(uz);
+            tx = fmaxf(tx, 0.f);
+            ty = fmaxf(ty, 0.f);
+            tz = fmaxf(tz, 0.f);
+            int axis = 0;
+            float s_exit = tx;
+            if (ty < s_exit) { s_exit = ty; axis = 1; }
+            if (tz < s_exit) { s_exit = tz; axis = 2; }
+            if (K * s_exit >= tau) {
+                const float sc = tau * rcp(K);
+                px += sc * ux;
+                py += sc * uy;
+                pz += sc * uz;
+                outcome = kCollision;
+                break;
+            }
+            tau -= K * s_exit;
+            px += s_exit * ux;
+            py += s_exit * uy;
+            pz += s_exit * uz;
+            if (axis == 2) {
+                if (uz < 0.f) {
+                    if (bk == 0) { pz = 0.f; outcome = kSurface; break; }
+                    --bk;
+                    pz = (float)(bk + 1) * P.cz;
+                } else {
+                    if (bk == P.mz - 1) { outcome = kEscape; break; }
+                    ++bk;
+                    pz = (float)bk * P.cz;
+                }
+            } else if (axis == 0) {
+                if (ux > 0.f) {
+                    bi = bi + 1 == P.mx ? 0 : bi + 1;
+                    px = (float)bi * P.cx;
+                } else {
+                    bi = bi == 0 ? P.mx - 1 : bi - 1;
+                    px = (float)(bi + 1) * P.cx;
+                }
+            } else {
+                if (uy > 0.f) {
+                    bj = bj + 1 == P.my ? 0 : bj + 1;
+                    py = (float)bj * P.cy;
+                } else {
+                    bj = bj == 0 ? P.my - 1 : bj - 1;
+                    py = (float)(bj + 1) * P.cy;
+                }
+            }
+            ++n_cross;
+        }
+
+        if (outcome == kCollision) {
+            // ---- tentative collision: local properties from the fine grid
+            const int i = cell_ix(px, P.inv_dx, bi, P.bx);
+            const int j = cell_ix(py, P.inv_dy, bj, P.by);
+            const int k = cell_ix(pz, P.inv_dz, bk, P.bz);
             const uint32_t cell = (uint32_t)((k * P.ny + j) * P.nx + i);
-            const float ke = P.k_ext[cell];
-            const float om = P.ssa[cell];
+            const float4 c = P.cells[cell];
+            const float ke = c.x, om = c.y;
             const float ka = ke * (1.0f - om);
+            const float iK = rcp(K);
             ++n_coll;
             if (ka > 0.f) {
-                uint32_t dep = (uint32_t)rintf((float)w * (ka * rcp(K)));
-                dep = min(dep, w);
+                const uint32_t dep = min(w, (uint32_t)rintf((float)w * (ka * iK)));
                 const uint32_t key = cell | (direct ? 0u : 0x80000000u);
                 if (key != pend_key) {
                     flush_deposit();
@@ -348,104 +385,72 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
                     continue;
                 }
             }
-            const float ks = ke * om;
+            // scattering with probability k_sca / (K - k_abs), else null
             const float den = K - ka;
-            const float ps = den > 0.f ? ks / den : 0.f;
-            const float xi = u01(r1);
+            const float ps = den > 0.f ? (ke * om) * rcp(den) : 0.f;
+            const float xi = u01(r.y);
             if (xi < ps) {
-                const float kc = P.k_cld[cell];
                 float mu;
-                if (xi * ke < ps * kc) {
-                    mu = hg_cos(P.g[cell], u01(r2));
+                if (xi * ke < ps * c.z) {
+                    mu = hg_cos(c.w, u01(r.z));
                     ++n_cloud;
                 } else {
-                    mu = rayleigh_cos(u01(r2));
+                    mu = rayleigh_cos(u01(r.z));
                     ++n_gas;
                 }
-                turn(ux, uy, uz, mu, u01(r3));
+                turn(ux, uy, uz, mu, u01(r.w));
                 direct = false;
             } else {
                 ++n_null;
             }
-            roulette();  // counter (id, step, 1): same free-path index
+            roulette();
             ++step;
-            need_tau = true;
             continue;
         }
-
-        // ---- cross into the next acceleration-grid cell
-        tau -= K * s_exit;
-        px += s_exit * ux;
-        py += s_exit * uy;
-        pz += s_exit * uz;
-        if (axis == 2) {
-            if (uz < 0.f && bk == 0) {
-                // ---- Lambertian surface (sec. 2.3)
-                pz = 0.f;
-                const int i = min(max((int)floorf(px * P.inv_dx), bi * P.bx), bi * P.bx + P.bx - 1);
-                const int j = min(max((int)floorf(py * P.inv_dy), bj * P.by), bj * P.by + P.by - 1);
-                const int c2 = j * P.nx + i;
-                atomicAdd(direct ? &P.sfc_dir[c2] : &P.sfc_dif[c2], (unsigned long long)w);
-                const uint32_t wn = min(w, (uint32_t)rintf(P.albedo[c2] * (float)w));
-                if (w != wn) {
-                    atomicAdd(&P.sfc_abs[c2], (unsigned long long)(w - wn));
-                    lds_add(&s_ledger[L_SFC], w - wn);
-                }
-                atomicAdd(&s_stats[S_SFC], 1ull);
-                w = wn;
-                if (w == 0) {
-                    atomicAdd(&s_stats[S_ABSORBED], 1ull);
-                    finish_photon();
-                    continue;
-                }
-                const float mu = sqrtf(u01_open(r2));
-                float sp, cp;
-                __sincosf(6.28318530717958647f * u01(r3), &sp, &cp);
-                const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
-                ux = st * cp;
-                uy = st * sp;
-                uz = mu;
-                direct = false;
-                roulette();
-                ++step;
-                need_tau = true;
-                continue;
+        if (outcome == kSurface) {
+            // ---- Lambertian surface (sec. 2.3)
+            const int i = cell_ix(px, P.inv_dx, bi, P.bx);
+            const int j = cell_ix(py, P.inv_dy, bj, P.by);
+            const int c2 = j * P.nx + i;
+            atomicAdd(direct ? &P.sfc_dir[c2] : &P.sfc_dif[c2], (unsigned long long)w);
+            const uint32_t wn = min(w, (uint32_t)rintf(P.albedo[c2] * (float)w));
+            if (w != wn) {
+                atomicAdd(&P.sfc_abs[c2], (unsigned long long)(w - wn));
+                lds_add(&s_ledger[L_SFC], w - wn);
             }
-            if (uz > 0.f && bk == P.mz - 1) {
-                // ---- leaves through the top of the domain
-                const int i = min(max((int)floorf(px * P.inv_dx), bi * P.bx), bi * P.bx + P.bx - 1);
-                const int j = min(max((int)floorf(py * P.inv_dy), bj * P.by), bj * P.by + P.by - 1);
-                atomicAdd(&P.toa_up[j * P.nx + i], (unsigned long long)w);
-                lds_add(&s_ledger[L_TOA], w);
-                atomicAdd(&s_stats[S_ESC], 1ull);
+            atomicAdd(&s_stats[S_SFC], 1ull);
+            w = wn;
+            if (w == 0) {
+                atomicAdd(&s_stats[S_ABSORBED], 1ull);
                 finish_photon();
                 continue;
             }
-            if (uz > 0.f) {
-                ++bk;
-                pz = (float)bk * P.cz;
-            } else {
-                --bk;
-                pz = (float)(bk + 1) * P.cz;
-            }
-        } else if (axis == 0) {
-            if (ux > 0.f) {
-                bi = bi + 1 == P.mx ? 0 : bi + 1;
-                px = (float)bi * P.cx;
-            } else {
-                bi = bi == 0 ? P.mx - 1 : bi - 1;
-                px = (float)(bi + 1) * P.cx;
-            }
-        } else {
-            if (uy > 0.f) {
-                bj = bj + 1 == P.my ? 0 : bj + 1;
-                py = (float)bj * P.cy;
-            } else {
-                bj = bj == 0 ? P.my - 1 : bj - 1;
-                py = (float)(bj + 1) * P.cy;
-            }
+            const float mu = sqrtf(u01_open(r.z));
+            float sp, cp;
+            __sincosf(6.28318530717958647f * u01(r.w), &sp, &cp);
+            const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+            ux = st * cp;
+            uy = st * sp;
+            uz = mu;
+            direct = false;
+            roulette();
+            ++step;
+            continue;
         }
-        ++n_cross;
+        if (outcome == kEscape) {
+            // ---- leaves through the top of the domain
+            const int i = cell_ix(px, P.inv_dx, bi, P.bx);
+            const int j = cell_ix(py, P.inv_dy, bj, P.by);
+            atomicAdd(&P.toa_up[j * P.nx + i], (unsigned long long)w);
+            lds_add(&s_ledger[L_TOA], w);
+            atomicAdd(&s_stats[S_ESC], 1ull);
+            finish_photon();
+            continue;
+        }
+        // iteration cap reached
+        lds_add(&s_ledger[L_LOST], w);
+        atomicAdd(&s_stats[S_CAPPED], 1ull);
+        finish_photon();
     }
 
     flush_deposit();
@@ -454,6 +459,15 @@ __global__ void __launch_bounds__(kBlock) trace_kernel(const TraceParams P) {
     __syncthreads();
     if (threadIdx.x < L_N && s_ledger[threadIdx.x]) atomicAdd(&P.ledger[threadIdx.x], s_ledger[threadIdx.x]);
     if (threadIdx.x < S_N && s_stats[threadIdx.x]) atomicAdd(&P.stats[threadIdx.x], s_stats[threadIdx.x]);
+}
+
+// Interleave the four SoA property arrays into one 16-byte record per cell,
+// so a tentative collision needs a single random 16-byte gather.
+__global__ void pack_cells_kernel(const float* __restrict__ ke, const float* __restrict__ om,
+                                  const float* __restrict__ kc, const float* __restrict__ g,
+                                  float4* __restrict__ out, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = make_float4(ke[i], om[i], kc[i], g[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -630,7 +644,7 @@ size_t rt3d_workspace_size(const rt3d_grid* grid, const rt3d_options* opt) {
     resolve_options(grid, opt, &o);
     Shape s;
     if (!shape_of(grid, &o, &s)) return 0;
-    return kCtrlBytes + align256(s.nmaj * sizeof(float));
+    return kCtrlBytes + align256(s.nmaj * sizeof(float)) + align256(s.ncell * sizeof(float4));
 }
 
 rt3d_status rt3d_majorant_build(const rt3d_grid* grid, const float* k_ext, int32_t bx, int32_t by, int32_t bz,
@@ -679,6 +693,7 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, c
     unsigned long long* queue = (unsigned long long*)ws;
     uint32_t* flag = (uint32_t*)(ws + 128);
     float* maj = (float*)(ws + kCtrlBytes);
+    float4* cells = (float4*)(ws + kCtrlBytes + align256(s.nmaj * sizeof(float)));
 
     // control block: queue counter and validation flag
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(32), 0, st, (unsigned long long*)ws, kCtrlBytes / 8, 0ull);
@@ -711,10 +726,10 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, c
 
     TraceParams P;
     memset(&P, 0, sizeof P);
-    P.k_ext = props->k_ext;
-    P.k_cld = props->k_ext_cloud;
-    P.ssa = props->ssa;
-    P.g = props->g;
+    hipLaunchKernelGGL(pack_cells_kernel, dim3(grid_for(s.ncell, 256, 16384)), dim3(256), 0, st, props->k_ext,
+                       props->ssa, props->k_ext_cloud, props->g, cells, s.ncell);
+    HIP_TRY(hipGetLastError());
+    P.cells = cells;
     P.albedo = surface_albedo;
     P.majorant = maj;
     P.abs_dir = (unsigned long long*)out->abs_dir;
@@ -763,13 +778,14 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, c
     HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t maj_bytes = s.nmaj * sizeof(float);
     const size_t lds_limit = o.lds_majorant > 0 ? (size_t)max_lds - 1024 : kLdsMajorantBytes;
-    P.lds_majorant = (o.lds_majorant >= 0 && maj_bytes <= lds_limit && maj_bytes + 1024 <= (size_t)max_lds) ? 1 : 0;
-    const size_t lds = P.lds_majorant ? maj_bytes : 0;
+    const bool use_lds = o.lds_majorant >= 0 && maj_bytes <= lds_limit && maj_bytes + 1024 <= (size_t)max_lds;
+    const size_t lds = use_lds ? maj_bytes : 0;
+    auto kernel = use_lds ? trace_kernel<true> : trace_kernel<false>;
 
     int ncu = 0;
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_kernel, kBlock, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds));
     if (per_cu < 1) per_cu = 1;
     unsigned blocks = o.grid_blocks ? (unsigned)o.grid_blocks : (unsigned)(ncu * per_cu);
     // never more lanes than photons need
@@ -782,7 +798,7 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, c
         if (!g_t1) HIP_TRY(hipEventCreate(&g_t1));
         HIP_TRY(hipEventRecord(g_t0, st));
     }
-    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(kBlock), lds, st, P);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), lds, st, P);
     HIP_TRY(hipGetLastError());
     if (o.flags & RT3D_FLAG_TIME) {
         HIP_TRY(hipEventRecord(g_t1, st));

@@ -62,7 +62,7 @@ def test_workspace_size_host_only(lib):
     g = Grid(256, 256, 128, 50.0, 50.0, 25.0)
     o = rt3d.options(brick=(8, 8, 8))
     n = rt3d.workspace_size(g, o)
-    assert n == 256 + 32 * 32 * 16 * 4
+    assert n == 256 + 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16  # control, majorants, packed cells
     bad = rt3d.options(brick=(3, 8, 8))
     with pytest.raises(rt3d.Rt3dError):
         rt3d.workspace_size(g, bad)

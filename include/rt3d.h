@@ -176,6 +176,9 @@ enum {
                                      (synchronises the stream) */
 #define RT3D_FLAG_TIME 0x4u       /* time the tracing kernel with HIP events;
                                      read with rt3d_last_trace_ms */
+#define RT3D_FLAG_NO_MERGE 0x8u   /* one tally atomic per deposit instead of
+                                     merging a lane's consecutive deposits
+                                     into the same cell (same results) */
 
 typedef struct {
     /* acceleration-grid cell ("brick") in fine cells; must divide nx, ny, nz */
@@ -191,7 +194,31 @@ typedef struct {
     int32_t block_threads;   /* threads per workgroup, 0 = automatic */
     int32_t lds_majorant;    /* stage the majorant grid in LDS: 0 = automatic,
                                 1 = when it fits, -1 = never */
+    int32_t max_walk;        /* acceleration-grid crossings a lane makes per
+                                loop iteration before the wave re-converges;
+                                0 = automatic (unbounded with LDS majorants) */
+    int32_t pool_photons;    /* photon ids a wave takes from the work queue
+                                at a time, 0 = 256 */
 } rt3d_options;
+
+/* Several g-points in one launch (sec. 2.2: 112 shortwave quadrature points;
+ * sec. 2.3: each traced independently).  Factored medium: the gas of each
+ * g-point is horizontally uniform, the cloud field is shared by all
+ * g-points.  For g-point n and cell (i,j,k) the optical properties are
+ *   k_ext = k_gas[n][k] + k_cloud[k][j][i],  k_ext,cloud = k_cloud[k][j][i],
+ *   omega0 k_ext = ssa_gas[n][k] k_gas[n][k] + ssa_cloud[k][j][i] k_cloud,
+ *   g = g_cloud[k][j][i] (gas scatters with the Rayleigh phase function).
+ * Device FP32 pointers; k_gas, ssa_gas are [n_gpoints][nz]; the cloud
+ * fields are [nz][ny][nx].                                                 */
+typedef struct {
+    const float* k_gas;
+    const float* ssa_gas;
+    const float* k_cloud;
+    const float* ssa_cloud;
+    const float* g_cloud;
+} rt3d_batched_medium;
+
+#define RT3D_MAX_GPOINTS 256
 
 /* ---------------------------------------------------------------------- */
 
@@ -234,8 +261,29 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props,
                        const rt3d_options* opt, const rt3d_tallies* out,
                        void* workspace, size_t workspace_bytes, void* stream);
 
-/* Milliseconds spent in the tracing kernel of the last rt3d_trace call made
- * with RT3D_FLAG_TIME on this thread (waits for it to finish).  Host *ms. */
+/* Bytes of device workspace rt3d_trace_batched needs (per-g-point majorant
+ * grids, packed cloud records, gas tables).  Returns 0 on bad input. */
+size_t rt3d_workspace_size_batched(const rt3d_grid* grid, int32_t n_gpoints, const rt3d_options* opt);
+
+/* Trace n_gpoints g-points (1 <= n_gpoints <= RT3D_MAX_GPOINTS) of the
+ * factored medium in ONE persistent launch and write broadband raw tallies
+ * (the sum over g-points) to `out`.  photons: HOST array [n_gpoints] of photon
+ * counts (zeros allowed, total > 0); g-point n is traced exactly as
+ * rt3d_trace would trace its fields with photons[n] photons and Philox key
+ * seed + n, so with photon counts proportional to the g-points' shares of
+ * the TOD flux every photon carries the same energy and the broadband tally
+ * normalised by the total photon count is the flux-weighted sum.  Each
+ * g-point has its own majorant grid (max over its fine cells of k_gas +
+ * k_cloud).  opt->photon_offset must be 0.  Other arguments and errors as
+ * rt3d_trace; RT3D_FLAG_VALIDATE checks every input range. */
+rt3d_status rt3d_trace_batched(const rt3d_grid* grid, int32_t n_gpoints, const rt3d_batched_medium* medium,
+                               const uint64_t* photons, const float* surface_albedo, double sza_deg,
+                               double azimuth_deg, uint64_t seed, const rt3d_options* opt,
+                               const rt3d_tallies* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Milliseconds spent in the tracing kernel of the last rt3d_trace or
+ * rt3d_trace_batched call made with RT3D_FLAG_TIME on this thread (waits for
+ * it to finish).  Host *ms. */
 rt3d_status rt3d_last_trace_ms(float* ms);
 
 /* Normalise raw tallies (sec. 2.3: fluxes are mean weights; heating is the

@@ -1,0 +1,186 @@
+"""Autotuner for the tracer's launch options.
+
+Picks the acceleration-grid cell ("brick") shape, the crossings a lane makes
+per loop iteration, the persistent grid size, the photon-id pool a wave takes
+per refill and the tally-merging mode from short calibration runs.  The
+objective is tracing-kernel time per photon (HIP events around the kernel),
+not events/s: looser majorants inflate the event count without doing more
+useful work.  Every candidate traces the same photons through the same
+fields, so the choice changes only speed, never the estimator's expectation.
+
+Results are cached in a JSON file keyed by device, library build, grid,
+sun geometry and a fingerprint of the fields.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import json
+import os
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import rt3d
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rt3d", "autotune.json")
+
+BRICKS = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 8, 4), (8, 8, 16), (4, 4, 8), (16, 16, 8), (16, 16, 4)]
+WALKS = [0, 1, 2, 4, 8]
+POOLS = [64, 256, 1024]
+
+
+@dataclasses.dataclass
+class TuneResult:
+    options: dict                      # keyword arguments for rt3d.trace / trace_batched
+    ms_per_photon: float               # calibration kernel time per photon (ms)
+    table: List[dict]                  # every candidate measured
+    cached: bool = False
+
+
+def _divides(grid, b) -> bool:
+    return grid.nx % b[0] == 0 and grid.ny % b[1] == 0 and grid.nz % b[2] == 0
+
+
+def _fingerprint(arrays, extra) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        v = a.detach().reshape(-1)
+        step = max(1, v.numel() // 4096)
+        h.update(v[::step].float().cpu().numpy().tobytes())
+    h.update(json.dumps(extra, sort_keys=True).encode())
+    return h.hexdigest()[:16]
+
+
+def _lib_hash() -> str:
+    with open(rt3d.LIB_PATH, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, cache):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=None, pools=None,
+            grid_mults=(1,), try_merge=True):
+    """Staged coordinate search; run(opts) returns kernel ms for `sample` photons."""
+    table = []
+
+    def measure(opts):
+        ms = min(run(opts) for _ in range(2))
+        table.append({**{k: (list(v) if isinstance(v, tuple) else v) for k, v in opts.items()},
+                      "kernel_ms": ms, "ms_per_photon": ms / sample})
+        return ms
+
+    best = {"brick": (8, 8, 8) if _divides(grid, (8, 8, 8)) else (1, 1, 1)}
+    best_ms = float("inf")
+    for b in (bricks or BRICKS):
+        if not _divides(grid, b):
+            continue
+        ms = measure({"brick": b})
+        if ms < best_ms:
+            best_ms, best = ms, {"brick": b}
+    for wk in (walks or WALKS):
+        if wk == 0:
+            continue
+        o = {**best, "max_walk": wk}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
+    for pool in (pools or POOLS):
+        if pool == 256:
+            continue
+        o = {**best, "pool_photons": pool}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for m in grid_mults:   # persistent workgroups per CU below full occupancy
+        o = {**best, "grid_blocks": int(ncu * m)}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
+    if try_merge:
+        o = {**best, "merge": False}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
+    return best, best_ms, table
+
+
+def tune_trace(df: "rt3d.DeviceFields", sza: float, azimuth: float, sample: int = 1 << 22, seed: int = 77,
+               cache_path: Optional[str] = DEFAULT_CACHE, force: bool = False, **search_kw) -> TuneResult:
+    """Tune rt3d.trace for these fields and sun; returns the best options."""
+    key = "|".join([torch.cuda.get_device_name(0), _lib_hash(), "trace",
+                    f"{df.grid.nx}x{df.grid.ny}x{df.grid.nz}",
+                    _fingerprint([df.k_ext, df.ssa, df.k_ext_cloud], {"sza": sza, "az": azimuth, "n": sample})])
+    cache = _load_cache(cache_path) if cache_path else {}
+    if not force and key in cache:
+        c = cache[key]
+        return TuneResult(_opts_from_json(c["options"]), c["ms_per_photon"], c["table"], cached=True)
+    out = rt3d.alloc_tallies(df.grid)
+
+    def run(opts):
+        o = dict(opts)
+        rt3d.trace(df, sza, azimuth, sample, seed, out=out, timed=True, **o)
+        return rt3d.last_trace_ms()
+
+    search_kw.setdefault("grid_mults", (1,))
+    best, best_ms, table = _search(run, df.grid, sample, **search_kw)
+    res = TuneResult(best, best_ms / sample, table)
+    if cache_path:
+        cache[key] = {"options": _opts_to_json(best), "ms_per_photon": res.ms_per_photon, "table": table}
+        _store_cache(cache_path, cache)
+    return res
+
+
+def tune_batched(dm: "rt3d.DeviceBatchedMedium", sza: float, azimuth: float, photons, sample: int = 1 << 22,
+                 seed: int = 77, cache_path: Optional[str] = DEFAULT_CACHE, force: bool = False,
+                 **search_kw) -> TuneResult:
+    """Tune rt3d.trace_batched: the calibration uses the g-points' photon
+    shares scaled down to `sample` photons in total."""
+    counts = np.asarray(photons, dtype=np.float64)
+    share = np.floor(counts / counts.sum() * sample).astype(np.uint64)
+    share[np.argmax(counts)] += np.uint64(sample - int(share.sum()))
+    key = "|".join([torch.cuda.get_device_name(0), _lib_hash(), "batched",
+                    f"{dm.grid.nx}x{dm.grid.ny}x{dm.grid.nz}x{dm.n_gpoints}",
+                    _fingerprint([dm.k_gas, dm.k_cloud, dm.ssa_gas],
+                                 {"sza": sza, "az": azimuth, "n": sample, "share": share.tolist()})])
+    cache = _load_cache(cache_path) if cache_path else {}
+    if not force and key in cache:
+        c = cache[key]
+        return TuneResult(_opts_from_json(c["options"]), c["ms_per_photon"], c["table"], cached=True)
+    out = rt3d.alloc_tallies(dm.grid)
+
+    def run(opts):
+        rt3d.trace_batched(dm, sza, azimuth, share, seed, out=out, timed=True, **opts)
+        return rt3d.last_trace_ms()
+
+    search_kw.setdefault("grid_mults", (3, 4))
+    best, best_ms, table = _search(run, dm.grid, sample, **search_kw)
+    res = TuneResult(best, best_ms / sample, table)
+    if cache_path:
+        cache[key] = {"options": _opts_to_json(best), "ms_per_photon": res.ms_per_photon, "table": table}
+        _store_cache(cache_path, cache)
+    return res
+
+
+def _opts_to_json(o: dict) -> dict:
+    return {k: (list(v) if isinstance(v, tuple) else v) for k, v in o.items()}
+
+
+def _opts_from_json(o: dict) -> dict:
+    return {k: (tuple(v) if isinstance(v, list) else v) for k, v in o.items()}

@@ -34,10 +34,8 @@
 namespace {
 
 constexpr uint32_t kWOne = 0x80000000u;  // weight one in units of 2^-31
-constexpr int kBlock = 1024;             // threads per workgroup
-constexpr uint32_t kPool = 256;          // photon ids fetched per wave refill
 constexpr uint32_t kNoCell = 0xffffffffu;
-constexpr size_t kLdsMajorantBytes = 64 * 1024;  // automatic LDS staging limit
+constexpr size_t kLdsMajorantBytes = 64 * 1024;  // automatic LDS staging limit (two workgroups per CU)
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): per round the counter becomes
@@ -105,9 +103,15 @@ __device__ __forceinline__ void turn(float& x, float& y, float& z, float mu, flo
 }
 
 struct TraceParams {
-    const float4* __restrict__ cells;  // packed (k_ext, ssa, k_ext_cloud, g) per cell
+    // medium: kFactored = false: cells = (k_ext, ssa, k_ext_cloud, g) per cell;
+    //         kFactored = true:  cells = (k_ext_cloud, cloud k_abs, g, 0) per cell,
+    //                            gas = (k_gas, gas k_abs) per g-point and level
+    const float4* __restrict__ cells;
+    const float2* __restrict__ gas;
     const float* __restrict__ albedo;
-    const float* __restrict__ majorant;
+    const float* __restrict__ majorant;                    // [ngp][nmaj]
+    const unsigned long long* __restrict__ gp_first;       // [ngp + 1] first photon of each g-point
+    const unsigned long long* __restrict__ gp_col_offset;  // [ngp]
     unsigned long long* abs_dir;
     unsigned long long* abs_dif;
     unsigned long long* sfc_dir;
@@ -117,16 +121,19 @@ struct TraceParams {
     unsigned long long* ledger;
     unsigned long long* stats;
     unsigned long long* queue;
+    int ngp, nmaj, max_walk;
+    uint32_t pool;   // photon ids a wave takes from the queue at a time
+    int merge;       // merge consecutive deposits of a lane into one cell
     int nx, ny, nz, bx, by, bz, mx, my, mz;
     float dx, dy, dz, inv_dx, inv_dy, inv_dz;
     float cx, cy, cz;  // acceleration-grid cell size in metres
     float H;
     float sun_x, sun_y, sun_z;
     float diffuse_fraction;
-    uint32_t key0, key1;
     uint32_t rr_below;
     uint32_t max_iters;
-    unsigned long long photons, photon_offset, ncol, col_offset;
+    unsigned long long seed;  // g-point n draws with Philox key seed + n
+    unsigned long long photons, photon_offset, ncol;
 };
 
 enum { L_IN, L_TOA, L_ATM_DIR, L_ATM_DIF, L_SFC, L_RR_GAIN, L_RR_LOSS, L_LOST, L_N };
@@ -142,74 +149,116 @@ __device__ __forceinline__ uint64_t lane_mask_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-enum Outcome { kCollision = 0, kSurface = 1, kEscape = 2, kCapped = 3 };
+enum Outcome { kCollision = 0, kSurface = 1, kEscape = 2, kCapped = 3, kWalking = 4 };
 
-// One workgroup = kBlock lanes, one photon per lane.  Each loop iteration of
+// Local optical properties at a tentative collision: extinction, absorption,
+// scattering and cloud extinction coefficients, cloud asymmetry.
+struct Local {
+    float ke, ka, ks, kc, g;
+};
+
+template <bool kFactored>
+__device__ __forceinline__ Local local_props(const TraceParams& P, int gp, uint32_t cell, int k) {
+    const float4 c = P.cells[cell];
+    Local L;
+    if (!kFactored) {
+        L.ke = c.x;
+        L.ka = c.x * (1.0f - c.y);
+        L.ks = c.x * c.y;
+        L.kc = c.z;
+        L.g = c.w;
+    } else {
+        const float2 q = P.gas[gp * P.nz + k];
+        L.ke = q.x + c.x;
+        L.ka = q.y + c.y;
+        L.ks = (q.x - q.y) + (c.x - c.y);
+        L.kc = c.x;
+        L.g = c.z;
+    }
+    return L;
+}
+
+// One photon per lane.  Each loop iteration of
 // a lane: (re)fill the lane with a new photon if it has none, draw the free
-// path's four random words, walk acceleration-grid cells until the tentative
-// collision / surface / top, then handle that event.  kLds selects the
-// majorant grid in LDS (staged once per workgroup) or read through L1/L2.
-template <bool kLds>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) trace_kernel(const TraceParams P) {
+// path's four random words, walk acceleration-grid cells (at most
+// P.max_walk crossings per iteration) until the tentative collision /
+// surface / top, then handle that event.  kLds: majorant grid of the single
+// g-point staged in LDS.  kFactored: shared cloud field + per-g-point gas
+// profiles (several g-points in one launch).
+// Launch shape: the single-g-point kernel runs 1024-lane workgroups at 8
+// waves per SIMD (two workgroups per CU share the 160 KB LDS); the factored
+// kernel needs more registers and runs 256-lane workgroups at 6 waves.
+template <bool kFactored>
+struct Shape_ {
+    static constexpr int threads = kFactored ? 256 : 1024;
+    static constexpr int waves = kFactored ? 6 : 8;
+};
+
+template <bool kLds, bool kFactored>
+__global__ void __launch_bounds__(Shape_<kFactored>::threads)
+    __attribute__((amdgpu_waves_per_eu(Shape_<kFactored>::waves))) trace_kernel(const TraceParams P) {
     extern __shared__ float s_maj[];
     __shared__ unsigned long long s_ledger[L_N];
     __shared__ unsigned long long s_stats[S_N];
+    __shared__ unsigned long long s_passes, s_absorbed_coll;
 
     if (threadIdx.x < L_N) s_ledger[threadIdx.x] = 0;
     if (threadIdx.x < S_N) s_stats[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_passes = s_absorbed_coll = 0;
     if (kLds) {
-        const int nmaj = P.mx * P.my * P.mz;
-        for (int i = threadIdx.x; i < nmaj; i += blockDim.x) s_maj[i] = P.majorant[i];
+        for (int i = threadIdx.x; i < P.nmaj; i += blockDim.x) s_maj[i] = P.majorant[i];
     }
     __syncthreads();
-    const float* __restrict__ maj = kLds ? s_maj : P.majorant;
 
     // ---- per-lane photon state
     bool alive = false;
     unsigned long long id = 0;
+    int gp = 0;
     float px = 0.f, py = 0.f, pz = 0.f, ux = 0.f, uy = 0.f, uz = -1.f;
     int bi = 0, bj = 0, bk = 0;
+    float tau = -1.f;  // optical depth left on the current free path; < 0: draw a new one
     uint32_t w = 0, step = 0, iters = 0;
     bool direct = false;
     // merged deposit: cell index, bit 31 set for diffuse
     uint32_t pend_key = kNoCell;
     unsigned long long pend_amt = 0;
-    // per-photon counters (folded into LDS when the photon ends)
-    uint32_t n_coll = 0, n_null = 0, n_gas = 0, n_cloud = 0, n_cross = 0;
-    unsigned long long atm_dir = 0, atm_dif = 0;
+    // per-photon counters (folded into LDS when the photon ends).  Brick
+    // crossings and null collisions are derived when the workgroup ends:
+    // crossings = passes - collisions - surface hits - escapes - capped,
+    // null = collisions - scatterings - photons absorbed at a collision.
+    uint32_t n_coll = 0, n_scat = 0;  // n_scat: gas in the low, cloud in the high 16 bits
 
-    // ---- per-wave photon-id pool (wave-uniform)
+    // ---- per-wave photon-id pool (wave-uniform, kept in scalar registers)
     unsigned long long pool_next = 0, pool_end = 0;
     bool drained = false;
 
     auto flush_deposit = [&]() {
         if (pend_amt) {
             const uint32_t cell = pend_key & 0x7fffffffu;
-            if (pend_key & 0x80000000u) {
-                atomicAdd(&P.abs_dif[cell], pend_amt);
-                atm_dif += pend_amt;
-            } else {
-                atomicAdd(&P.abs_dir[cell], pend_amt);
-                atm_dir += pend_amt;
-            }
+            atomicAdd(pend_key & 0x80000000u ? &P.abs_dif[cell] : &P.abs_dir[cell], pend_amt);
         }
         pend_key = kNoCell;
         pend_amt = 0;
     };
+    auto flush_scat = [&]() {
+        lds_add(&s_stats[S_GAS], n_scat & 0xffffu);
+        lds_add(&s_stats[S_CLOUD], n_scat >> 16);
+        n_scat = 0;
+    };
     auto finish_photon = [&]() {
         alive = false;
         lds_add(&s_stats[S_COLL], n_coll);
-        lds_add(&s_stats[S_NULL], n_null);
-        lds_add(&s_stats[S_GAS], n_gas);
-        lds_add(&s_stats[S_CLOUD], n_cloud);
-        lds_add(&s_stats[S_CROSS], n_cross);
-        n_coll = n_null = n_gas = n_cloud = n_cross = 0;
+        lds_add(&s_passes, iters);
+        flush_scat();
+        n_coll = 0;
     };
+    auto key0 = [&]() { return (uint32_t)(P.seed + (unsigned long long)(kFactored ? gp : 0)); };
+    auto key1 = [&]() { return (uint32_t)((P.seed + (unsigned long long)(kFactored ? gp : 0)) >> 32); };
     // Russian roulette (sec. 2.3) with the current free path's counter
     // (id, step, 1): survive with probability w, then weight one.
     auto roulette = [&]() {
         if (w >= P.rr_below) return;
-        const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 1u), P.key0, P.key1);
+        const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 1u), key0(), key1());
         if ((q.x >> 1) < w) {
             lds_add(&s_ledger[L_RR_GAIN], kWOne - w);
             atomicAdd(&s_stats[S_RR_SURV], 1ull);
@@ -233,26 +282,39 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
             const unsigned long long avail = pool_end - pool_next;
             unsigned long long base = 0;
             if (avail < need) {
-                if ((int)__lane_id() == leader) base = atomicAdd(P.queue, (unsigned long long)kPool);
+                if ((int)__lane_id() == leader) base = atomicAdd(P.queue, (unsigned long long)P.pool);
                 base = __shfl(base, leader);
+                base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       __builtin_amdgcn_readfirstlane((uint32_t)base);
             }
             if (!alive) {
                 const uint32_t rank = (uint32_t)__popcll(dead & lane_mask_lt());
                 const unsigned long long local = rank < avail ? pool_next + rank : base + (rank - avail);
                 if (local < P.photons) {
+                    // g-point of this photon: its range [gp_first[n], gp_first[n+1])
+                    gp = 0;
+                    if (kFactored && P.ngp > 1) {
+                        int lo = 0, hi = P.ngp;  // gp_first[lo] <= local < gp_first[hi]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (P.gp_first[mid] <= local) lo = mid;
+                            else hi = mid;
+                        }
+                        gp = lo;
+                    }
                     // ---- emission at the top of the domain (sec. 2.3)
-                    id = P.photon_offset + local;
-                    const unsigned long long col = (id + P.col_offset) % P.ncol;
+                    id = P.photon_offset + (local - P.gp_first[gp]);
+                    const unsigned long long col = (id + P.gp_col_offset[gp]) % P.ncol;
                     const int ic = (int)(col % (unsigned)P.nx);
                     const int jc = (int)(col / (unsigned)P.nx);
                     const uint4 e = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 0u),
-                                           P.key0, P.key1);
+                                           key0(), key1());
                     px = ((float)ic + u01(e.x)) * P.dx;
                     py = ((float)jc + u01(e.y)) * P.dy;
                     pz = P.H;
                     if (u01(e.z) < P.diffuse_fraction) {
                         const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 1u),
-                                               P.key0, P.key1);
+                                               key0(), key1());
                         const float mu = sqrtf(u01_open(q.x));
                         float sp, cp;
                         __sincosf(6.28318530717958647f * u01(q.y), &sp, &cp);
@@ -273,6 +335,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
                     w = kWOne;
                     step = 0;
                     iters = 0;
+                    tau = -1.f;
                     alive = true;
                     atomicAdd(&s_stats[S_PHOT], 1ull);
                     lds_add(&s_ledger[L_IN], kWOne);
@@ -280,7 +343,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
             }
             if (avail < need) {
                 pool_next = base + (need - avail);
-                pool_end = base + kPool;
+                pool_end = base + P.pool;
             } else {
                 pool_next += need;
             }
@@ -292,16 +355,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
         if (!alive) continue;
 
         // ---- random words of this free path: tau, event, cos(theta), phi
-        const uint4 r = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 0u), P.key0, P.key1);
-        float tau = -__logf(u01_open(r.x));
+        const uint4 r = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), step, 0u), key0(), key1());
+        if (tau < 0.f) tau = -__logf(u01_open(r.x));
+        const int maj_base = kFactored ? gp * P.nmaj : 0;  // this g-point's majorant grid
 
         // ---- walk acceleration-grid cells until the path ends
         int outcome;
         float K;
-        for (;;) {
+        for (int walked = 0;; ++walked) {
             if (iters >= P.max_iters) { outcome = kCapped; break; }
+            if (walked >= P.max_walk) { outcome = kWalking; break; }
             ++iters;
-            K = maj[(bk * P.my + bj) * P.mx + bi];
+            K = kLds ? s_maj[(bk * P.my + bj) * P.mx + bi] : P.majorant[maj_base + (bk * P.my + bj) * P.mx + bi];
             const float x0 = (float)bi * P.cx, y0 = (float)bj * P.cy, z0 = (float)bk * P.cz;
             float tx = INFINITY, ty = INFINITY, tz = INFINITY;
             if (ux > 0.f) tx = (x0 + P.cx - px) * rcp(ux);
@@ -356,8 +421,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
                     py = (float)(bj + 1) * P.cy;
                 }
             }
-            ++n_cross;
         }
+        if (outcome == kWalking) continue;  // same free path next iteration
+        tau = -1.f;
 
         if (outcome == kCollision) {
             // ---- tentative collision: local properties from the fine grid
@@ -365,43 +431,42 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
             const int j = cell_ix(py, P.inv_dy, bj, P.by);
             const int k = cell_ix(pz, P.inv_dz, bk, P.bz);
             const uint32_t cell = (uint32_t)((k * P.ny + j) * P.nx + i);
-            const float4 c = P.cells[cell];
-            const float ke = c.x, om = c.y;
-            const float ka = ke * (1.0f - om);
+            const Local L = local_props<kFactored>(P, gp, cell, k);
             const float iK = rcp(K);
             ++n_coll;
-            if (ka > 0.f) {
-                const uint32_t dep = min(w, (uint32_t)rintf((float)w * (ka * iK)));
+            if (L.ka > 0.f) {
+                const uint32_t dep = min(w, (uint32_t)rintf((float)w * (L.ka * iK)));
                 const uint32_t key = cell | (direct ? 0u : 0x80000000u);
                 if (key != pend_key) {
                     flush_deposit();
                     pend_key = key;
                 }
                 pend_amt += dep;
+                if (!P.merge) flush_deposit();
                 w -= dep;
                 if (w == 0) {
                     atomicAdd(&s_stats[S_ABSORBED], 1ull);
+                    atomicAdd(&s_absorbed_coll, 1ull);
                     finish_photon();
                     continue;
                 }
             }
             // scattering with probability k_sca / (K - k_abs), else null
-            const float den = K - ka;
-            const float ps = den > 0.f ? (ke * om) * rcp(den) : 0.f;
+            const float den = K - L.ka;
+            const float ps = den > 0.f ? L.ks * rcp(den) : 0.f;
             const float xi = u01(r.y);
             if (xi < ps) {
                 float mu;
-                if (xi * ke < ps * c.z) {
-                    mu = hg_cos(c.w, u01(r.z));
-                    ++n_cloud;
+                if (xi * L.ke < ps * L.kc) {
+                    mu = hg_cos(L.g, u01(r.z));
+                    n_scat += 0x10000u;
                 } else {
                     mu = rayleigh_cos(u01(r.z));
-                    ++n_gas;
+                    n_scat += 1u;
                 }
                 turn(ux, uy, uz, mu, u01(r.w));
                 direct = false;
-            } else {
-                ++n_null;
+                if ((n_scat & 0x8000u) | (n_scat & 0x80000000u)) flush_scat();
             }
             roulette();
             ++step;
@@ -454,11 +519,34 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
     }
 
     flush_deposit();
-    lds_add(&s_ledger[L_ATM_DIR], atm_dir);
-    lds_add(&s_ledger[L_ATM_DIF], atm_dif);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_stats[S_CROSS] = s_passes - s_stats[S_COLL] - s_stats[S_SFC] - s_stats[S_ESC] - s_stats[S_CAPPED];
+        s_stats[S_NULL] = s_stats[S_COLL] - s_stats[S_GAS] - s_stats[S_CLOUD] - s_absorbed_coll;
+    }
     __syncthreads();
     if (threadIdx.x < L_N && s_ledger[threadIdx.x]) atomicAdd(&P.ledger[threadIdx.x], s_ledger[threadIdx.x]);
     if (threadIdx.x < S_N && s_stats[threadIdx.x]) atomicAdd(&P.stats[threadIdx.x], s_stats[threadIdx.x]);
+}
+
+// Heating entries of the energy ledger: ledger[ATM_DIR] = sum(abs_dir),
+// ledger[ATM_DIF] = sum(abs_dif), exact uint64 sums (the other entries are
+// counted by the tracing kernel, so the identity still checks that no
+// deposit was lost).  One workgroup per array.
+__global__ void ledger_atm_kernel(const unsigned long long* __restrict__ abs_dir,
+                                  const unsigned long long* __restrict__ abs_dif, size_t n,
+                                  unsigned long long* __restrict__ ledger) {
+    __shared__ unsigned long long part[1024];
+    const unsigned long long* src = blockIdx.x == 0 ? abs_dir : abs_dif;
+    unsigned long long acc = 0;
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x) acc += src[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ledger[blockIdx.x == 0 ? L_ATM_DIR : L_ATM_DIF] = part[0];
 }
 
 // Interleave the four SoA property arrays into one 16-byte record per cell,
@@ -468,6 +556,96 @@ __global__ void pack_cells_kernel(const float* __restrict__ ke, const float* __r
                                   float4* __restrict__ out, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         out[i] = make_float4(ke[i], om[i], kc[i], g[i]);
+}
+
+// Factored medium: per cell (k_ext_cloud, cloud k_abs, g, 0).
+__global__ void pack_cloud_kernel(const float* __restrict__ kc, const float* __restrict__ om,
+                                  const float* __restrict__ g, float4* __restrict__ out, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float k = kc[i];
+        out[i] = make_float4(k, k * (1.0f - om[i]), g[i], 0.0f);
+    }
+}
+
+// Factored medium: per g-point and level (k_gas, gas k_abs).
+__global__ void pack_gas_kernel(const float* __restrict__ kg, const float* __restrict__ om, float2* __restrict__ out,
+                                size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float k = kg[i];
+        out[i] = make_float2(k, k * (1.0f - om[i]));
+    }
+}
+
+// Factored majorant, step 1: per level k and acceleration column (bi, bj),
+// the largest cloud extinction: layer[k][bj][bi] (FP32 bits, integer max).
+__global__ void layer_max_kernel(const float4* __restrict__ cells, uint32_t* __restrict__ layer, int nx, int ny,
+                                 int nz, int bx, int by) {
+    const int mx = nx / bx, my = ny / by;
+    const size_t n = (size_t)mx * ny * nz;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int bi = (int)(t % mx);
+        const size_t row = t / mx;  // j + ny * k
+        const int j = (int)(row % ny);
+        const int k = (int)(row / ny);
+        const float4* src = cells + row * nx + (size_t)bi * bx;
+        uint32_t m = 0;
+        for (int q = 0; q < bx; ++q) {
+            const float v = src[q].x;
+            const uint32_t bits = v > 0.0f ? __float_as_uint(v) : 0u;
+            m = bits > m ? bits : m;
+        }
+        atomicMax(&layer[((size_t)k * my + j / by) * mx + bi], m);
+    }
+}
+
+// Factored majorant, step 2: K[n][bk][bj][bi] = max over the levels k of
+// brick layer bk of (k_gas[n][k] + layer[k][bj][bi]).  FP32 addition is
+// monotonic, so this equals the largest k_gas + k_cloud of the cells.
+__global__ void gas_majorant_kernel(const uint32_t* __restrict__ layer, const float2* __restrict__ gas,
+                                    float* __restrict__ maj, int ngp, int nz, int mx, int my, int bz) {
+    const int mz = nz / bz;
+    const size_t nmaj = (size_t)mx * my * mz;
+    const size_t n = nmaj * ngp;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int gp = (int)(t / nmaj);
+        const size_t b = t % nmaj;
+        const size_t col = b % ((size_t)mx * my);
+        const int bk = (int)(b / ((size_t)mx * my));
+        float m = 0.0f;
+        for (int q = 0; q < bz; ++q) {
+            const int k = bk * bz + q;
+            const float v = gas[(size_t)gp * nz + k].x + __uint_as_float(layer[(size_t)k * mx * my + col]);
+            m = v > m ? v : m;
+        }
+        maj[t] = m;
+    }
+}
+
+// Per-g-point photon ranges and systematic-sampling column offsets (Philox
+// counter (0, 0, 0xfffffffe, 0) under the g-point's key, word 0).
+constexpr int kMaxGpoints = 256;
+struct BatchInit {
+    unsigned long long photons[kMaxGpoints];
+    unsigned long long seed, ncol;
+    int ngp;
+};
+
+__global__ void batch_init_kernel(const BatchInit a, unsigned long long* __restrict__ gp_first,
+                                  unsigned long long* __restrict__ gp_col_offset) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        unsigned long long acc = 0;
+        for (int n = 0; n < a.ngp; ++n) {
+            gp_first[n] = acc;
+            acc += a.photons[n];
+        }
+        gp_first[a.ngp] = acc;
+    }
+    for (int n = t; n < a.ngp; n += blockDim.x) {
+        const unsigned long long key = a.seed + (unsigned long long)n;
+        const uint4 r = philox(make_uint4(0u, 0u, 0xfffffffeu, 0u), (uint32_t)key, (uint32_t)(key >> 32));
+        gp_col_offset[n] = ((unsigned long long)r.x * a.ncol) >> 32;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -519,6 +697,27 @@ __global__ void validate_kernel(const float* __restrict__ ke, const float* __res
         bad |= ok ? 0u : 1u;
     }
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ncol; i += (size_t)gridDim.x * blockDim.x) {
+        const float a = alb[i];
+        bad |= (a >= 0.f && a <= 1.f) ? 0u : 1u;
+    }
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
+__global__ void validate_batched_kernel(const float* __restrict__ kg, const float* __restrict__ og, size_t ngas,
+                                        const float* __restrict__ kc, const float* __restrict__ oc,
+                                        const float* __restrict__ g, const float* __restrict__ alb, size_t ncell,
+                                        size_t ncol, uint32_t* flag) {
+    uint32_t bad = 0;
+    const size_t s0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, st = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = s0; i < ngas; i += st) {
+        const float a = kg[i], b = og[i];
+        bad |= (a >= 0.f && a < INFINITY && b >= 0.f && b <= 1.f) ? 0u : 1u;
+    }
+    for (size_t i = s0; i < ncell; i += st) {
+        const float a = kc[i], b = oc[i], d = g[i];
+        bad |= (a >= 0.f && a < INFINITY && b >= 0.f && b <= 1.f && d >= -1.f && d <= 1.f) ? 0u : 1u;
+    }
+    for (size_t i = s0; i < ncol; i += st) {
         const float a = alb[i];
         bad |= (a >= 0.f && a <= 1.f) ? 0u : 1u;
     }
@@ -609,6 +808,210 @@ rt3d_status zero_u64(unsigned long long* p, size_t n, hipStream_t st) {
     return RT3D_OK;
 }
 
+
+// Workspace layout (every section 256-byte aligned):
+//   control  256 B: photon-id queue counter, validation flag
+//   meta     photon ranges [ngp + 1] and column offsets [ngp] (uint64)
+//   maj      majorants [ngp][nmaj] FP32
+//   cells    packed per-cell records [ncell] float4
+//   gas      factored only: (k_gas, gas k_abs) [ngp][nz] float2
+//   layer    factored only: per-level cloud maxima [nz][my][mx] uint32
+struct Layout {
+    size_t meta, maj, cells, gas, layer, total;
+};
+
+Layout layout_of(const Shape& s, int ngp, bool factored) {
+    Layout l;
+    size_t off = kCtrlBytes;
+    l.meta = off;
+    off += align256(sizeof(unsigned long long) * (2 * (size_t)ngp + 1));
+    l.maj = off;
+    off += align256(sizeof(float) * s.nmaj * ngp);
+    l.cells = off;
+    off += align256(sizeof(float4) * s.ncell);
+    l.gas = l.layer = 0;
+    if (factored) {
+        l.gas = off;
+        off += align256(sizeof(float2) * (size_t)ngp * s.nz);
+        l.layer = off;
+        off += align256(sizeof(uint32_t) * (size_t)s.nz * s.my * s.mx);
+    }
+    l.total = off;
+    return l;
+}
+
+struct Launch {
+    rt3d_options o;
+    Shape s;
+    int ngp;
+    unsigned long long total;
+    char* ws;
+    uint32_t* flag;
+    float* maj;
+    float4* cells;
+    float2* gas;
+    uint32_t* layer;
+    TraceParams P;
+};
+
+rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, const float* albedo, double sza_deg,
+                    double azimuth_deg, uint64_t seed, const rt3d_options* opt, const rt3d_tallies* out,
+                    void* workspace, size_t workspace_bytes, void* stream, bool factored, Launch* L) {
+    if (!grid_ok(grid)) return RT3D_EINVAL;
+    resolve_options(grid, opt, &L->o);
+    const rt3d_options& o = L->o;
+    if (!shape_of(grid, &o, &L->s)) return RT3D_EINVAL;
+    const Shape& s = L->s;
+    if (!albedo || !photons) return RT3D_EINVAL;
+    if (!out || !out->abs_dir || !out->abs_dif || !out->sfc_dir || !out->sfc_dif || !out->sfc_abs ||
+        !out->toa_up || !out->ledger || !out->stats)
+        return RT3D_EINVAL;
+    if (!(sza_deg >= 0.0 && sza_deg < 90.0) || !std::isfinite(azimuth_deg)) return RT3D_EINVAL;
+    if (!(o.diffuse_fraction >= 0.f && o.diffuse_fraction <= 1.f)) return RT3D_EINVAL;
+    if (!(o.rr_threshold >= 0.f && o.rr_threshold <= 1.f)) return RT3D_EINVAL;
+    if (o.grid_blocks < 0 || o.block_threads < 0 || o.max_walk < 0 || o.pool_photons < 0) return RT3D_EINVAL;
+    if (o.block_threads && o.block_threads != (factored ? Shape_<true>::threads : Shape_<false>::threads))
+        return RT3D_EINVAL;
+    unsigned long long total = 0;
+    for (int n = 0; n < ngp; ++n) {
+        if (total + photons[n] < total) return RT3D_EINVAL;
+        total += photons[n];
+    }
+    if (total == 0) return RT3D_EINVAL;
+    if (o.photon_offset + total < o.photon_offset) return RT3D_EINVAL;
+    const Layout lay = layout_of(s, ngp, factored);
+    if (!workspace || workspace_bytes < lay.total || ((uintptr_t)workspace & 255)) return RT3D_EINVAL;
+
+    L->ngp = ngp;
+    L->total = total;
+    L->ws = (char*)workspace;
+    L->flag = (uint32_t*)(L->ws + 128);
+    L->maj = (float*)(L->ws + lay.maj);
+    L->cells = (float4*)(L->ws + lay.cells);
+    L->gas = factored ? (float2*)(L->ws + lay.gas) : nullptr;
+    L->layer = factored ? (uint32_t*)(L->ws + lay.layer) : nullptr;
+    unsigned long long* gp_first = (unsigned long long*)(L->ws + lay.meta);
+    unsigned long long* gp_col = gp_first + ngp + 1;
+
+    hipStream_t st = (hipStream_t)stream;
+    // control block (queue counter, validation flag), photon ranges, column offsets
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(32), 0, st, (unsigned long long*)L->ws, kCtrlBytes / 8, 0ull);
+    HIP_TRY(hipGetLastError());
+    BatchInit bi;
+    memset(&bi, 0, sizeof bi);
+    for (int n = 0; n < ngp; ++n) bi.photons[n] = photons[n];
+    bi.seed = seed;
+    bi.ncol = s.ncol;
+    bi.ngp = ngp;
+    hipLaunchKernelGGL(batch_init_kernel, dim3(1), dim3(256), 0, st, bi, gp_first, gp_col);
+    HIP_TRY(hipGetLastError());
+
+    TraceParams& P = L->P;
+    memset(&P, 0, sizeof P);
+    P.cells = L->cells;
+    P.gas = L->gas;
+    P.albedo = albedo;
+    P.majorant = L->maj;
+    P.gp_first = gp_first;
+    P.gp_col_offset = gp_col;
+    P.abs_dir = (unsigned long long*)out->abs_dir;
+    P.abs_dif = (unsigned long long*)out->abs_dif;
+    P.sfc_dir = (unsigned long long*)out->sfc_dir;
+    P.sfc_dif = (unsigned long long*)out->sfc_dif;
+    P.sfc_abs = (unsigned long long*)out->sfc_abs;
+    P.toa_up = (unsigned long long*)out->toa_up;
+    P.ledger = (unsigned long long*)out->ledger;
+    P.stats = (unsigned long long*)out->stats;
+    P.queue = (unsigned long long*)L->ws;
+    P.ngp = ngp;
+    P.nmaj = (int)s.nmaj;
+    P.nx = s.nx; P.ny = s.ny; P.nz = s.nz;
+    P.bx = s.bx; P.by = s.by; P.bz = s.bz;
+    P.mx = s.mx; P.my = s.my; P.mz = s.mz;
+    P.dx = grid->dx; P.dy = grid->dy; P.dz = grid->dz;
+    P.inv_dx = 1.0f / grid->dx; P.inv_dy = 1.0f / grid->dy; P.inv_dz = 1.0f / grid->dz;
+    P.cx = (float)s.bx * grid->dx; P.cy = (float)s.by * grid->dy; P.cz = (float)s.bz * grid->dz;
+    P.H = (float)s.nz * grid->dz;
+    const double th = sza_deg * M_PI / 180.0, ph = azimuth_deg * M_PI / 180.0;
+    P.sun_x = (float)(-sin(th) * sin(ph));
+    P.sun_y = (float)(-sin(th) * cos(ph));
+    P.sun_z = (float)(-cos(th));
+    P.diffuse_fraction = o.diffuse_fraction;
+    P.rr_below = (uint32_t)std::nearbyint((double)o.rr_threshold * 2147483648.0);
+    P.max_iters = o.max_iters;
+    P.pool = o.pool_photons > 0 ? (uint32_t)o.pool_photons : 256u;
+    P.merge = (o.flags & RT3D_FLAG_NO_MERGE) ? 0 : 1;
+    P.seed = seed;
+    P.photons = total;
+    P.photon_offset = o.photon_offset;
+    P.ncol = s.ncol;
+    return RT3D_OK;
+}
+
+rt3d_status validated(const Launch& L, hipStream_t st) {
+    HIP_TRY(hipGetLastError());
+    uint32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, L.flag, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return h ? RT3D_EDOMAIN : RT3D_OK;
+}
+
+rt3d_status clear_outputs(const Launch& L, const rt3d_tallies* out, hipStream_t st) {
+    if (L.o.flags & RT3D_FLAG_ACCUMULATE) return RT3D_OK;
+    rt3d_status z;
+    if ((z = zero_u64((unsigned long long*)out->abs_dir, L.s.ncell, st)) != RT3D_OK) return z;
+    if ((z = zero_u64((unsigned long long*)out->abs_dif, L.s.ncell, st)) != RT3D_OK) return z;
+    if ((z = zero_u64((unsigned long long*)out->sfc_dir, L.s.ncol, st)) != RT3D_OK) return z;
+    if ((z = zero_u64((unsigned long long*)out->sfc_dif, L.s.ncol, st)) != RT3D_OK) return z;
+    if ((z = zero_u64((unsigned long long*)out->sfc_abs, L.s.ncol, st)) != RT3D_OK) return z;
+    if ((z = zero_u64((unsigned long long*)out->toa_up, L.s.ncol, st)) != RT3D_OK) return z;
+    if ((z = zero_u64((unsigned long long*)out->ledger, RT3D_LEDGER_N, st)) != RT3D_OK) return z;
+    return zero_u64((unsigned long long*)out->stats, RT3D_STATS_N, st);
+}
+
+rt3d_status launch_trace(Launch& L, bool factored, hipStream_t st) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t maj_bytes = L.s.nmaj * sizeof(float);
+    const size_t lds_limit = L.o.lds_majorant > 0 ? (size_t)max_lds - 1024 : kLdsMajorantBytes;
+    const bool use_lds =
+        L.ngp == 1 && L.o.lds_majorant >= 0 && maj_bytes <= lds_limit && maj_bytes + 1024 <= (size_t)max_lds;
+    const size_t lds = use_lds ? maj_bytes : 0;
+    // crossings per loop iteration: unbounded with majorants in LDS; with
+    // majorants read through L2 a short walk keeps the lanes in step
+    L.P.max_walk = L.o.max_walk > 0 ? L.o.max_walk : (use_lds ? 0x7fffffff : 2);
+    auto kernel = factored ? (use_lds ? trace_kernel<true, true> : trace_kernel<false, true>)
+                           : (use_lds ? trace_kernel<true, false> : trace_kernel<false, false>);
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int threads = factored ? Shape_<true>::threads : Shape_<false>::threads;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds));
+    if (per_cu < 1) per_cu = 1;
+    unsigned blocks = L.o.grid_blocks ? (unsigned)L.o.grid_blocks : (unsigned)(ncu * per_cu);
+    // never more lanes than photons need
+    const unsigned long long max_blocks = (L.total + threads - 1) / threads;
+    if (blocks > max_blocks) blocks = (unsigned)max_blocks;
+    if (blocks < 1) blocks = 1;
+    if (L.o.flags & RT3D_FLAG_TIME) {
+        if (!g_t0) HIP_TRY(hipEventCreate(&g_t0));
+        if (!g_t1) HIP_TRY(hipEventCreate(&g_t1));
+        HIP_TRY(hipEventRecord(g_t0, st));
+    }
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, st, L.P);
+    HIP_TRY(hipGetLastError());
+    if (L.o.flags & RT3D_FLAG_TIME) {
+        HIP_TRY(hipEventRecord(g_t1, st));
+        g_timed = true;
+    }
+    hipLaunchKernelGGL(ledger_atm_kernel, dim3(2), dim3(1024), 0, st, L.P.abs_dir, L.P.abs_dif, L.s.ncell,
+                       L.P.ledger);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -644,7 +1047,16 @@ size_t rt3d_workspace_size(const rt3d_grid* grid, const rt3d_options* opt) {
     resolve_options(grid, opt, &o);
     Shape s;
     if (!shape_of(grid, &o, &s)) return 0;
-    return kCtrlBytes + align256(s.nmaj * sizeof(float)) + align256(s.ncell * sizeof(float4));
+    return layout_of(s, 1, false).total;
+}
+
+size_t rt3d_workspace_size_batched(const rt3d_grid* grid, int32_t n_gpoints, const rt3d_options* opt) {
+    rt3d_options o;
+    if (!grid_ok(grid) || n_gpoints < 1 || n_gpoints > kMaxGpoints) return 0;
+    resolve_options(grid, opt, &o);
+    Shape s;
+    if (!shape_of(grid, &o, &s)) return 0;
+    return layout_of(s, n_gpoints, true).total;
 }
 
 rt3d_status rt3d_majorant_build(const rt3d_grid* grid, const float* k_ext, int32_t bx, int32_t by, int32_t bz,
@@ -669,142 +1081,66 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, c
                        const rt3d_options* opt, const rt3d_tallies* out, void* workspace, size_t workspace_bytes,
                        void* stream) {
     g_timed = false;
-    rt3d_options o;
-    if (!grid_ok(grid)) return RT3D_EINVAL;
-    resolve_options(grid, opt, &o);
-    Shape s;
-    if (!shape_of(grid, &o, &s)) return RT3D_EINVAL;
-    if (!props || !props->k_ext || !props->k_ext_cloud || !props->ssa || !props->g || !surface_albedo)
+    if (!props || !props->k_ext || !props->k_ext_cloud || !props->ssa || !props->g) return RT3D_EINVAL;
+    Launch L;
+    rt3d_status st = prepare(grid, 1, &photons, surface_albedo, sza_deg, azimuth_deg, seed, opt, out, workspace,
+                             workspace_bytes, stream, false, &L);
+    if (st != RT3D_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    if (L.o.flags & RT3D_FLAG_VALIDATE) {
+        hipLaunchKernelGGL(validate_kernel, dim3(grid_for(L.s.ncell, 256, 4096)), dim3(256), 0, hs, props->k_ext,
+                           props->k_ext_cloud, props->ssa, props->g, surface_albedo, L.s.ncell, L.s.ncol, L.flag);
+        if ((st = validated(L, hs)) != RT3D_OK) return st;
+    }
+    if ((st = clear_outputs(L, out, hs)) != RT3D_OK) return st;
+    if ((st = rt3d_majorant_build(grid, props->k_ext, L.s.bx, L.s.by, L.s.bz, L.maj, stream)) != RT3D_OK) return st;
+    hipLaunchKernelGGL(pack_cells_kernel, dim3(grid_for(L.s.ncell, 256, 16384)), dim3(256), 0, hs, props->k_ext,
+                       props->ssa, props->k_ext_cloud, props->g, L.cells, L.s.ncell);
+    HIP_TRY(hipGetLastError());
+    return launch_trace(L, false, hs);
+}
+
+rt3d_status rt3d_trace_batched(const rt3d_grid* grid, int32_t n_gpoints, const rt3d_batched_medium* medium,
+                               const uint64_t* photons, const float* surface_albedo, double sza_deg,
+                               double azimuth_deg, uint64_t seed, const rt3d_options* opt, const rt3d_tallies* out,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+    g_timed = false;
+    if (!medium || !medium->k_gas || !medium->ssa_gas || !medium->k_cloud || !medium->ssa_cloud ||
+        !medium->g_cloud || !photons)
         return RT3D_EINVAL;
-    if (!out || !out->abs_dir || !out->abs_dif || !out->sfc_dir || !out->sfc_dif || !out->sfc_abs ||
-        !out->toa_up || !out->ledger || !out->stats)
-        return RT3D_EINVAL;
-    if (!(sza_deg >= 0.0 && sza_deg < 90.0) || !std::isfinite(azimuth_deg) || photons == 0) return RT3D_EINVAL;
-    if (!(o.diffuse_fraction >= 0.f && o.diffuse_fraction <= 1.f)) return RT3D_EINVAL;
-    if (!(o.rr_threshold >= 0.f && o.rr_threshold <= 1.f)) return RT3D_EINVAL;
-    if (o.photon_offset + photons < o.photon_offset) return RT3D_EINVAL;
-    const size_t need = rt3d_workspace_size(grid, &o);
-    if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) return RT3D_EINVAL;
-    if (o.grid_blocks < 0 || o.block_threads < 0) return RT3D_EINVAL;
-    if (o.block_threads && o.block_threads != kBlock) return RT3D_EINVAL;
-
-    hipStream_t st = (hipStream_t)stream;
-    char* ws = (char*)workspace;
-    unsigned long long* queue = (unsigned long long*)ws;
-    uint32_t* flag = (uint32_t*)(ws + 128);
-    float* maj = (float*)(ws + kCtrlBytes);
-    float4* cells = (float4*)(ws + kCtrlBytes + align256(s.nmaj * sizeof(float)));
-
-    // control block: queue counter and validation flag
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(32), 0, st, (unsigned long long*)ws, kCtrlBytes / 8, 0ull);
+    if (n_gpoints < 1 || n_gpoints > kMaxGpoints) return RT3D_EINVAL;
+    if (opt && opt->photon_offset != 0) return RT3D_EINVAL;
+    Launch L;
+    rt3d_status st = prepare(grid, n_gpoints, photons, surface_albedo, sza_deg, azimuth_deg, seed, opt, out,
+                             workspace, workspace_bytes, stream, true, &L);
+    if (st != RT3D_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    if (L.o.flags & RT3D_FLAG_VALIDATE) {
+        hipLaunchKernelGGL(validate_batched_kernel, dim3(grid_for(L.s.ncell, 256, 4096)), dim3(256), 0, hs,
+                           medium->k_gas, medium->ssa_gas, (size_t)n_gpoints * L.s.nz, medium->k_cloud,
+                           medium->ssa_cloud, medium->g_cloud, surface_albedo, L.s.ncell, L.s.ncol, L.flag);
+        if ((st = validated(L, hs)) != RT3D_OK) return st;
+    }
+    if ((st = clear_outputs(L, out, hs)) != RT3D_OK) return st;
+    const size_t ngas = (size_t)n_gpoints * L.s.nz;
+    hipLaunchKernelGGL(pack_cloud_kernel, dim3(grid_for(L.s.ncell, 256, 16384)), dim3(256), 0, hs, medium->k_cloud,
+                       medium->ssa_cloud, medium->g_cloud, L.cells, L.s.ncell);
     HIP_TRY(hipGetLastError());
-
-    if (o.flags & RT3D_FLAG_VALIDATE) {
-        hipLaunchKernelGGL(validate_kernel, dim3(grid_for(s.ncell, 256, 4096)), dim3(256), 0, st, props->k_ext,
-                           props->k_ext_cloud, props->ssa, props->g, surface_albedo, s.ncell, s.ncol, flag);
-        HIP_TRY(hipGetLastError());
-        uint32_t h = 0;
-        HIP_TRY(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (h) return RT3D_EDOMAIN;
-    }
-
-    if (!(o.flags & RT3D_FLAG_ACCUMULATE)) {
-        rt3d_status z;
-        if ((z = zero_u64((unsigned long long*)out->abs_dir, s.ncell, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->abs_dif, s.ncell, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->sfc_dir, s.ncol, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->sfc_dif, s.ncol, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->sfc_abs, s.ncol, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->toa_up, s.ncol, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->ledger, RT3D_LEDGER_N, st)) != RT3D_OK) return z;
-        if ((z = zero_u64((unsigned long long*)out->stats, RT3D_STATS_N, st)) != RT3D_OK) return z;
-    }
-
-    rt3d_status ms = rt3d_majorant_build(grid, props->k_ext, s.bx, s.by, s.bz, maj, stream);
-    if (ms != RT3D_OK) return ms;
-
-    TraceParams P;
-    memset(&P, 0, sizeof P);
-    hipLaunchKernelGGL(pack_cells_kernel, dim3(grid_for(s.ncell, 256, 16384)), dim3(256), 0, st, props->k_ext,
-                       props->ssa, props->k_ext_cloud, props->g, cells, s.ncell);
+    hipLaunchKernelGGL(pack_gas_kernel, dim3(grid_for(ngas)), dim3(256), 0, hs, medium->k_gas, medium->ssa_gas,
+                       L.gas, ngas);
     HIP_TRY(hipGetLastError());
-    P.cells = cells;
-    P.albedo = surface_albedo;
-    P.majorant = maj;
-    P.abs_dir = (unsigned long long*)out->abs_dir;
-    P.abs_dif = (unsigned long long*)out->abs_dif;
-    P.sfc_dir = (unsigned long long*)out->sfc_dir;
-    P.sfc_dif = (unsigned long long*)out->sfc_dif;
-    P.sfc_abs = (unsigned long long*)out->sfc_abs;
-    P.toa_up = (unsigned long long*)out->toa_up;
-    P.ledger = (unsigned long long*)out->ledger;
-    P.stats = (unsigned long long*)out->stats;
-    P.queue = queue;
-    P.nx = s.nx; P.ny = s.ny; P.nz = s.nz;
-    P.bx = s.bx; P.by = s.by; P.bz = s.bz;
-    P.mx = s.mx; P.my = s.my; P.mz = s.mz;
-    P.dx = grid->dx; P.dy = grid->dy; P.dz = grid->dz;
-    P.inv_dx = 1.0f / grid->dx; P.inv_dy = 1.0f / grid->dy; P.inv_dz = 1.0f / grid->dz;
-    P.cx = (float)s.bx * grid->dx; P.cy = (float)s.by * grid->dy; P.cz = (float)s.bz * grid->dz;
-    P.H = (float)s.nz * grid->dz;
-    const double th = sza_deg * M_PI / 180.0, ph = azimuth_deg * M_PI / 180.0;
-    P.sun_x = (float)(-sin(th) * sin(ph));
-    P.sun_y = (float)(-sin(th) * cos(ph));
-    P.sun_z = (float)(-cos(th));
-    P.diffuse_fraction = o.diffuse_fraction;
-    P.key0 = (uint32_t)seed;
-    P.key1 = (uint32_t)(seed >> 32);
-    P.rr_below = (uint32_t)std::nearbyint((double)o.rr_threshold * 2147483648.0);
-    P.max_iters = o.max_iters;
-    P.photons = photons;
-    P.photon_offset = o.photon_offset;
-    P.ncol = s.ncol;
-    // run offset of the systematic column sampling: counter (0, 0, 0xfffffffe, 0), word 0
-    {
-        uint32_t c[4] = {0u, 0u, 0xfffffffeu, 0u};
-        uint32_t k0 = P.key0, k1 = P.key1;
-        for (int r = 0; r < 10; ++r) {
-            if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-            const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
-            const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-            c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
-        }
-        P.col_offset = ((unsigned long long)c[0] * (unsigned long long)s.ncol) >> 32;
-    }
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    int max_lds = 0;
-    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t maj_bytes = s.nmaj * sizeof(float);
-    const size_t lds_limit = o.lds_majorant > 0 ? (size_t)max_lds - 1024 : kLdsMajorantBytes;
-    const bool use_lds = o.lds_majorant >= 0 && maj_bytes <= lds_limit && maj_bytes + 1024 <= (size_t)max_lds;
-    const size_t lds = use_lds ? maj_bytes : 0;
-    auto kernel = use_lds ? trace_kernel<true> : trace_kernel<false>;
-
-    int ncu = 0;
-    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds));
-    if (per_cu < 1) per_cu = 1;
-    unsigned blocks = o.grid_blocks ? (unsigned)o.grid_blocks : (unsigned)(ncu * per_cu);
-    // never more lanes than photons need
-    const unsigned long long max_blocks = (photons + kBlock - 1) / kBlock;
-    if (blocks > max_blocks) blocks = (unsigned)max_blocks;
-    if (blocks < 1) blocks = 1;
-
-    if (o.flags & RT3D_FLAG_TIME) {
-        if (!g_t0) HIP_TRY(hipEventCreate(&g_t0));
-        if (!g_t1) HIP_TRY(hipEventCreate(&g_t1));
-        HIP_TRY(hipEventRecord(g_t0, st));
-    }
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), lds, st, P);
+    const size_t nlayer = (size_t)L.s.nz * L.s.my * L.s.mx;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nlayer)), dim3(256), 0, hs, L.layer, nlayer, 0u);
     HIP_TRY(hipGetLastError());
-    if (o.flags & RT3D_FLAG_TIME) {
-        HIP_TRY(hipEventRecord(g_t1, st));
-        g_timed = true;
-    }
-    return RT3D_OK;
+    const size_t nrow = (size_t)L.s.mx * L.s.ny * L.s.nz;
+    hipLaunchKernelGGL(layer_max_kernel, dim3(grid_for(nrow, 256, 16384)), dim3(256), 0, hs, L.cells, L.layer,
+                       L.s.nx, L.s.ny, L.s.nz, L.s.bx, L.s.by);
+    HIP_TRY(hipGetLastError());
+    const size_t nm = L.s.nmaj * (size_t)n_gpoints;
+    hipLaunchKernelGGL(gas_majorant_kernel, dim3(grid_for(nm, 256, 16384)), dim3(256), 0, hs, L.layer, L.gas,
+                       L.maj, n_gpoints, L.s.nz, L.s.mx, L.s.my, L.s.bz);
+    HIP_TRY(hipGetLastError());
+    return launch_trace(L, true, hs);
 }
 
 rt3d_status rt3d_last_trace_ms(float* ms) {

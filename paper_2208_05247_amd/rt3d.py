@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librt3d.so")
 
 OK, EINVAL, EDOMAIN, EDEVICE = 0, 1, 2, 3
-FLAG_ACCUMULATE, FLAG_VALIDATE, FLAG_TIME = 0x1, 0x2, 0x4
+FLAG_ACCUMULATE, FLAG_VALIDATE, FLAG_TIME, FLAG_NO_MERGE = 0x1, 0x2, 0x4, 0x8
 LEDGER = ("incoming", "toa", "atm_dir", "atm_dif", "sfc", "rr_gain", "rr_loss", "lost")
 STATS = ("photons", "collisions", "null", "scat_gas", "scat_cloud", "surface", "escape",
          "rr_kill", "rr_survive", "crossings", "absorbed", "capped")
@@ -28,7 +28,9 @@ TALLY3 = ("abs_dir", "abs_dif")
 TALLY2 = ("sfc_dir", "sfc_dif", "sfc_abs", "toa_up")
 EXPORTS = ("rt3d_abi_version", "rt3d_status_string", "rt3d_last_device_error",
            "rt3d_default_options", "rt3d_workspace_size", "rt3d_majorant_build",
-           "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize", "rt3d_philox4x32_10")
+           "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize", "rt3d_philox4x32_10",
+           "rt3d_workspace_size_batched", "rt3d_trace_batched")
+MAX_GPOINTS = 256
 
 
 class Rt3dError(RuntimeError):
@@ -56,7 +58,13 @@ class Options(ctypes.Structure):
                 ("diffuse_fraction", ctypes.c_float), ("rr_threshold", ctypes.c_float),
                 ("flags", ctypes.c_uint32), ("max_iters", ctypes.c_uint32),
                 ("photon_offset", ctypes.c_uint64), ("grid_blocks", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("lds_majorant", ctypes.c_int32)]
+                ("block_threads", ctypes.c_int32), ("lds_majorant", ctypes.c_int32),
+                ("max_walk", ctypes.c_int32), ("pool_photons", ctypes.c_int32)]
+
+
+class BatchedMedium(ctypes.Structure):
+    _fields_ = [("k_gas", ctypes.c_void_p), ("ssa_gas", ctypes.c_void_p), ("k_cloud", ctypes.c_void_p),
+                ("ssa_cloud", ctypes.c_void_p), ("g_cloud", ctypes.c_void_p)]
 
 
 _lib = None
@@ -85,11 +93,16 @@ def load(path: str = LIB_PATH):
                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Options),
                                ctypes.POINTER(TalliesStruct), P, Z, P]
     lib.rt3d_last_trace_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
+    lib.rt3d_workspace_size_batched.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(Options)]
+    lib.rt3d_workspace_size_batched.restype = Z
+    lib.rt3d_trace_batched.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(BatchedMedium), P, P,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Options),
+                                       ctypes.POINTER(TalliesStruct), P, Z, P]
     lib.rt3d_finalize.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(TalliesStruct), ctypes.c_uint64, P,
                                   ctypes.c_double, P, P, P, P, P, P, P]
     lib.rt3d_philox4x32_10.argtypes = [P, ctypes.c_uint64, P, ctypes.c_uint32, P]
     for name in ("rt3d_majorant_build", "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize",
-                 "rt3d_philox4x32_10"):
+                 "rt3d_philox4x32_10", "rt3d_trace_batched"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.rt3d_abi_version() != 1:
         raise RuntimeError("librt3d.so ABI version mismatch")
@@ -147,7 +160,8 @@ class DeviceFields:
 
 
 def options(brick=(8, 8, 8), diffuse_fraction=0.0, rr_threshold=0.5, flags=0, max_iters=0,
-            photon_offset=0, grid_blocks=0, block_threads=0, lds_majorant=0) -> Options:
+            photon_offset=0, grid_blocks=0, block_threads=0, lds_majorant=0, max_walk=0,
+            pool_photons=0) -> Options:
     o = Options()
     load().rt3d_default_options(ctypes.byref(o))
     o.brick_x, o.brick_y, o.brick_z = (int(b) for b in brick)
@@ -159,6 +173,8 @@ def options(brick=(8, 8, 8), diffuse_fraction=0.0, rr_threshold=0.5, flags=0, ma
     o.grid_blocks = int(grid_blocks)
     o.block_threads = int(block_threads)
     o.lds_majorant = int(lds_majorant)
+    o.max_walk = int(max_walk)
+    o.pool_photons = int(pool_photons)
     return o
 
 
@@ -192,7 +208,8 @@ def tallies_struct(t: dict) -> TalliesStruct:
 def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int, *,
           brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
           photon_offset: int = 0, accumulate: bool = False, validate: bool = False, timed: bool = False,
-          max_iters: int = 0, grid_blocks: int = 0, lds_majorant: int = 0, out: Optional[dict] = None,
+          max_iters: int = 0, grid_blocks: int = 0, lds_majorant: int = 0, max_walk: int = 0,
+          pool_photons: int = 0, merge: bool = True, out: Optional[dict] = None,
           workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
     """rt3d_trace: raw uint64 tallies (int64 tensors) of `photons` photons."""
     lib = load()
@@ -200,9 +217,9 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
     for n in ("k_ext", "k_ext_cloud", "ssa", "g", "albedo"):
         _require_device(getattr(df, n), n, torch.float32)
     flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
-            (FLAG_TIME if timed else 0)
+            (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, photon_offset, grid_blocks,
-                  lds_majorant=lds_majorant)
+                  lds_majorant=lds_majorant, max_walk=max_walk, pool_photons=pool_photons)
     gs = grid_struct(grid)
     nws = workspace_size(grid, opt)
     if workspace is None:
@@ -217,6 +234,73 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
                         workspace.numel() * workspace.element_size(), _stream(stream))
     _check(st, "rt3d_trace")
     out["photons"] = int(photons)
+    return out
+
+
+@dataclasses.dataclass
+class DeviceBatchedMedium:
+    """Factored medium of several g-points on the device: per-g-point gas
+    profiles [ngp][nz] and one shared cloud field [nz][ny][nx]."""
+    grid: object
+    k_gas: torch.Tensor
+    ssa_gas: torch.Tensor
+    k_cloud: torch.Tensor
+    ssa_cloud: torch.Tensor
+    g_cloud: torch.Tensor
+    albedo: torch.Tensor
+
+    @property
+    def n_gpoints(self) -> int:
+        return int(self.k_gas.shape[0])
+
+    @classmethod
+    def from_host(cls, medium, device="cuda") -> "DeviceBatchedMedium":
+        def up(a):
+            return torch.from_numpy(np.array(a, dtype=np.float32, copy=True)).to(device)
+        return cls(medium.grid, up(medium.k_gas), up(medium.ssa_gas), up(medium.k_cloud), up(medium.ssa_cloud),
+                   up(medium.g_cloud), up(medium.albedo))
+
+
+def workspace_size_batched(grid, n_gpoints: int, opt: Options) -> int:
+    n = load().rt3d_workspace_size_batched(ctypes.byref(grid_struct(grid)), int(n_gpoints), ctypes.byref(opt))
+    if n == 0:
+        raise Rt3dError(EINVAL, "rt3d_workspace_size_batched")
+    return int(n)
+
+
+def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: Sequence[int], seed: int, *,
+                  brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
+                  accumulate: bool = False, validate: bool = False, timed: bool = False, max_iters: int = 0,
+                  grid_blocks: int = 0, max_walk: int = 0, pool_photons: int = 0, merge: bool = True,
+                  out: Optional[dict] = None, workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
+    """rt3d_trace_batched: broadband raw tallies of all g-points in one launch."""
+    lib = load()
+    grid = dm.grid
+    for n in ("k_gas", "ssa_gas", "k_cloud", "ssa_cloud", "g_cloud", "albedo"):
+        _require_device(getattr(dm, n), n, torch.float32)
+    ngp = dm.n_gpoints
+    if len(photons) != ngp:
+        raise ValueError("one photon count per g-point")
+    flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
+            (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE)
+    opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, 0, grid_blocks, max_walk=max_walk,
+                  pool_photons=pool_photons)
+    gs = grid_struct(grid)
+    nws = workspace_size_batched(grid, ngp, opt)
+    if workspace is None:
+        workspace = alloc_workspace(nws, dm.k_cloud.device)
+    if out is None:
+        out = alloc_tallies(grid, dm.k_cloud.device)
+    med = BatchedMedium(dm.k_gas.data_ptr(), dm.ssa_gas.data_ptr(), dm.k_cloud.data_ptr(),
+                        dm.ssa_cloud.data_ptr(), dm.g_cloud.data_ptr())
+    counts = np.ascontiguousarray(np.asarray(photons, dtype=np.uint64))
+    ts = tallies_struct(out)
+    st = lib.rt3d_trace_batched(ctypes.byref(gs), ngp, ctypes.byref(med), counts.ctypes.data_as(ctypes.c_void_p),
+                                ctypes.c_void_p(dm.albedo.data_ptr()), float(sza), float(azimuth), int(seed),
+                                ctypes.byref(opt), ctypes.byref(ts), ctypes.c_void_p(workspace.data_ptr()),
+                                workspace.numel() * workspace.element_size(), _stream(stream))
+    _check(st, "rt3d_trace_batched")
+    out["photons"] = int(counts.sum())
     return out
 
 

@@ -225,3 +225,90 @@ def random_fields(grid: Grid, seed: int, k_max: float = 0.02, cloud_frac: float 
     kc32 = np.minimum(kc.astype(np.float32), ke32)
     return Fields(grid, ke32, kc32, ss.astype(np.float32), gg.astype(np.float32),
                   alb.astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# Several g-points: factored medium (per-g-point gas profiles, shared clouds)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class BatchedMedium:
+    """FP32 factored medium: k_gas, ssa_gas [ngp][nz]; k_cloud, ssa_cloud,
+    g_cloud [nz][ny][nx]; albedo [ny][nx]; flux weights [ngp]."""
+
+    grid: Grid
+    k_gas: np.ndarray
+    ssa_gas: np.ndarray
+    k_cloud: np.ndarray
+    ssa_cloud: np.ndarray
+    g_cloud: np.ndarray
+    albedo: np.ndarray
+    weights: np.ndarray
+
+    @property
+    def n_gpoints(self) -> int:
+        return int(self.k_gas.shape[0])
+
+    def fields_of(self, n: int) -> Fields:
+        """Full FP32 optical properties of g-point n (k_ext = k_gas + k_cloud,
+        omega0 k_ext = ssa_gas k_gas + ssa_cloud k_cloud)."""
+        kg = self.k_gas[n].astype(np.float64)[:, None, None]
+        og = self.ssa_gas[n].astype(np.float64)[:, None, None]
+        kc = self.k_cloud.astype(np.float64)
+        oc = self.ssa_cloud.astype(np.float64)
+        ke = kg + kc
+        with np.errstate(invalid="ignore", divide="ignore"):
+            om = np.where(ke > 0.0, (kg * og + kc * oc) / ke, 0.0)
+        ke32 = ke.astype(np.float32)
+        return Fields(self.grid, np.ascontiguousarray(ke32),
+                      np.ascontiguousarray(np.minimum(self.k_cloud, ke32)),
+                      np.ascontiguousarray(np.clip(om, 0.0, 1.0).astype(np.float32)),
+                      np.ascontiguousarray(self.g_cloud), self.albedo)
+
+
+@dataclasses.dataclass
+class BatchedWorkload:
+    name: str
+    medium: BatchedMedium
+    sza: float
+    azimuth: float
+    photons: np.ndarray  # per g-point
+    seed: int
+    brick: tuple
+
+
+def gpoint_set(grid: Grid, n_gp: int, rng: np.random.Generator, tau_range=(1e-3, 50.0),
+               ssa_range=(0.2, 1.0)):
+    """Synthetic shortwave g-points: gas column optical depth log-uniform in
+    tau_range with an exp(-z/8 km) profile, gas ssa uniform in ssa_range,
+    TOA flux weights Dirichlet(1)."""
+    tau = np.exp(rng.uniform(np.log(tau_range[0]), np.log(tau_range[1]), n_gp))
+    ssa = rng.uniform(*ssa_range, n_gp)
+    w = rng.dirichlet(np.ones(n_gp))
+    kg = np.stack([gas_profile_column_tau(grid, t) for t in tau]).astype(np.float32)
+    og = np.repeat(ssa[:, None], grid.nz, axis=1).astype(np.float32)
+    return kg, og, w
+
+
+def batched_cumulus(seed: int = 1, nx: int = 512, ny: int = 512, nz: int = 96, dx: float = 50.0,
+                    dz: float = 32.0, n_gp: int = 112, photons: int = 1 << 28, n_blobs=None,
+                    sza: float = 45.0, brick=(8, 8, 8), albedo=0.2) -> BatchedWorkload:
+    """Batched g-points over an LES-shaped cumulus field: 512x512x96 cells
+    of 50x50x32 m, 112 g-points, photon counts Multinomial(photons,
+    weights) so every photon carries the same energy."""
+    grid = Grid(nx, ny, nz, dx, dx, dz)
+    rng = np.random.default_rng(seed)
+    if n_blobs is None:
+        n_blobs = int(round(200 * (nx * ny) / (256 * 256)))
+    amp = lambda r: float(0.02 * np.exp(0.5 * r.standard_normal()))
+    kc = cloud_blobs(grid, rng, n_blobs, amp, z_range=(700.0, 2500.0), layer=(700.0, 2500.0),
+                     centre_margin=True).astype(np.float32)
+    oc = np.where(kc > 0, np.float32(0.9995), np.float32(0.0)).astype(np.float32)
+    gc = np.where(kc > 0, np.float32(0.86), np.float32(0.0)).astype(np.float32)
+    kg, og, w = gpoint_set(grid, n_gp, rng)
+    counts = rng.multinomial(photons, w).astype(np.uint64)
+    alb = np.full(grid.shape2, albedo, dtype=np.float32) if np.ndim(albedo) == 0 else \
+        np.ascontiguousarray(albedo, dtype=np.float32)
+    med = BatchedMedium(grid, kg, og, kc, oc, gc, alb, w)
+    return BatchedWorkload(f"batched_cumulus_{nx}x{ny}x{nz}_{n_gp}g", med, sza, 0.0, counts, seed,
+                           tuple(brick))

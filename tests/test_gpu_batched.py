@@ -1,0 +1,191 @@
+"""Batched g-points in one persistent launch (rt3d_trace_batched) and the
+launch options the autotuner varies.
+
+Bitwise: one batched launch equals the sum of single-g-point batched
+launches (keys seed + n); every launch option (crossings per iteration,
+LDS staging, photon pool, tally merging, grid size) leaves the uint64
+tallies unchanged.  Statistical: the broadband tallies agree with the FP64
+oracle run per g-point on the materialised fields and summed."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from mc_stats import compare_batches  # noqa: E402
+from paper_2208_05247_amd import synthetic as syn  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+W1 = 2 ** 31
+ARRAYS = ("abs_dir", "abs_dif", "sfc_dir", "sfc_dif", "sfc_abs", "toa_up")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rt3d():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_2208_05247_amd import rt3d as lib
+    lib.load()
+    return lib
+
+
+def ledger_ok(h, photons):
+    L = [int(v) for v in h["ledger"]]
+    inc, toa, adir, adif, sfc, gain, loss, lost = L
+    assert inc == photons * W1
+    assert inc + gain == toa + adir + adif + sfc + loss + lost
+    assert adir == int(h["abs_dir"].sum(dtype=np.uint64))
+    assert sfc == int(h["sfc_abs"].sum(dtype=np.uint64))
+    assert toa == int(h["toa_up"].sum(dtype=np.uint64))
+    S = dict(zip(oracle.STATS, [int(v) for v in h["stats"]]))
+    assert S["photons"] == photons == S["escape"] + S["rr_kill"] + S["absorbed"] + S["capped"]
+
+
+def small_batch(n_gp=6, photons=1 << 16, seed=3):
+    return syn.batched_cumulus(seed=seed, nx=32, ny=32, nz=32, dx=50.0, dz=50.0, n_gp=n_gp,
+                               photons=photons, n_blobs=6, brick=(4, 4, 4))
+
+
+def test_batched_equals_sum_of_single_gpoints(rt3d):
+    wl = small_batch()
+    m = wl.medium
+    counts = wl.photons.copy()
+    counts[2] = 0  # a g-point without photons
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    seed = 1234
+    full = rt3d.to_host(rt3d.trace_batched(dm, wl.sza, wl.azimuth, counts, seed, brick=wl.brick))
+    ledger_ok(full, int(counts.sum()))
+    acc = {k: np.zeros_like(full[k]) for k in ARRAYS + ("ledger", "stats")}
+    for n in range(m.n_gpoints):
+        if counts[n] == 0:
+            continue
+        one = syn.BatchedMedium(m.grid, m.k_gas[n:n + 1], m.ssa_gas[n:n + 1], m.k_cloud, m.ssa_cloud, m.g_cloud,
+                                m.albedo, m.weights[n:n + 1])
+        d1 = rt3d.DeviceBatchedMedium.from_host(one)
+        h = rt3d.to_host(rt3d.trace_batched(d1, wl.sza, wl.azimuth, [int(counts[n])], seed + n, brick=wl.brick))
+        for k in acc:
+            acc[k] += h[k]
+    for k in ARRAYS + ("ledger",):
+        assert np.array_equal(acc[k], full[k]), k
+    for i, name in enumerate(oracle.STATS):
+        assert acc["stats"][i] == full["stats"][i], name
+
+
+@pytest.mark.parametrize("kw", [dict(max_walk=1), dict(max_walk=3), dict(pool_photons=64),
+                                dict(pool_photons=1024), dict(merge=False), dict(grid_blocks=5)])
+def test_launch_options_do_not_change_tallies(rt3d, kw):
+    wl = syn.small_cumulus()
+    df = rt3d.DeviceFields.from_host(wl.fields)
+    ref = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 17, 5, brick=wl.brick))
+    got = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 17, 5, brick=wl.brick, **kw))
+    for k in ARRAYS + ("ledger", "stats"):
+        assert np.array_equal(ref[k], got[k]), (k, kw)
+    nolds = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 17, 5, brick=wl.brick, lds_majorant=-1, **kw))
+    for k in ARRAYS + ("ledger", "stats"):
+        assert np.array_equal(ref[k], nolds[k]), (k, "no LDS", kw)
+    bw = small_batch()
+    dm = rt3d.DeviceBatchedMedium.from_host(bw.medium)
+    b0 = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 9, brick=bw.brick))
+    b1 = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 9, brick=bw.brick, **kw))
+    for k in ARRAYS + ("ledger", "stats"):
+        assert np.array_equal(b0[k], b1[k]), (k, "batched", kw)
+
+
+def test_batched_parity_vs_oracle(rt3d):
+    """Broadband tallies of 6 g-points (gas optical depth 1e-3..50) vs the
+    oracle traced per g-point on materialised fields, 32 batches each."""
+    wl = small_batch(n_gp=6, photons=1 << 15, seed=5)
+    m = wl.medium
+    counts = [int(c) for c in wl.photons]
+    total = sum(counts)
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    grid = m.grid
+    B = 32
+    gpu = {k: [] for k in ARRAYS}
+    ora = {k: [] for k in ARRAYS}
+    fields = [m.fields_of(n) for n in range(m.n_gpoints)]
+    say("batched parity: gpu")
+    for b in range(B):
+        raw = rt3d.trace_batched(dm, wl.sza, wl.azimuth, counts, 1000 * b + 1, brick=wl.brick)
+        h = rt3d.to_host(raw)
+        ledger_ok(h, total)
+        fin = rt3d.finalize(grid, raw, total)
+        for k in ARRAYS:
+            gpu[k].append(fin[k].double().cpu().numpy())
+    say("batched parity: oracle")
+    for b in range(B):
+        acc = None
+        for n, f in enumerate(fields):
+            if counts[n] == 0:
+                continue
+            r = oracle.trace(f, wl.sza, wl.azimuth, counts[n], 500000 + 1000 * b + n, brick=wl.brick)
+            acc = r if acc is None else {k: acc[k] + r[k] for k in ARRAYS}
+        fin = oracle.finalize(acc, grid, total)
+        for k in ARRAYS:
+            ora[k].append(fin[k])
+    for k in ARRAYS:
+        g, o = np.stack(gpu[k]), np.stack(ora[k])
+        frac, n_dense, _, dense, z = compare_batches(g, o)
+        say("batched", k, frac, n_dense)
+        assert frac >= 0.998 and np.all(np.abs(z[dense]) < 5.5), k
+        if k.startswith("abs"):
+            ga, oa = g.sum(axis=(2, 3)), o.sum(axis=(2, 3))
+        else:
+            ga, oa = g.reshape(B, 8, 4, 8, 4).sum(axis=(2, 4)), o.reshape(B, 8, 4, 8, 4).sum(axis=(2, 4))
+        frac2, n2, _, dense2, z2 = compare_batches(ga, oa)
+        assert frac2 >= 0.99 and np.all(np.abs(z2[dense2]) < 5.5), (k, "aggregate")
+
+
+def test_batched_errors(rt3d):
+    wl = small_batch(n_gp=3)
+    m = wl.medium
+    bad = syn.BatchedMedium(m.grid, m.k_gas, m.ssa_gas.copy(), m.k_cloud, m.ssa_cloud, m.g_cloud, m.albedo,
+                            m.weights)
+    bad.ssa_gas[1, 4] = 1.5
+    with pytest.raises(rt3d.Rt3dError) as e:
+        rt3d.trace_batched(rt3d.DeviceBatchedMedium.from_host(bad), 30.0, 0.0, wl.photons, 1, brick=wl.brick,
+                           validate=True)
+    assert e.value.status == rt3d.EDOMAIN
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    rt3d.trace_batched(dm, 30.0, 0.0, wl.photons, 1, brick=wl.brick, validate=True)
+    with pytest.raises(rt3d.Rt3dError):
+        rt3d.trace_batched(dm, 30.0, 0.0, [0, 0, 0], 1, brick=wl.brick)
+    with pytest.raises(rt3d.Rt3dError):
+        rt3d.trace_batched(dm, 30.0, 0.0, wl.photons, 1, brick=(3, 4, 4))
+
+
+def test_batched_full_size_ledger_and_speed(rt3d):
+    """512x512x96 cells, 112 g-points, 2^28 photons in one launch: exact
+    ledger and bitwise rerun."""
+    wl = syn.batched_cumulus()
+    dm = rt3d.DeviceBatchedMedium.from_host(wl.medium)
+    total = int(wl.photons.sum())
+    a = rt3d.trace_batched(dm, wl.sza, wl.azimuth, wl.photons, 1, brick=wl.brick, timed=True)
+    ms = rt3d.last_trace_ms()
+    h = rt3d.to_host(a)
+    ledger_ok(h, total)
+    say("batched full: kernel ms", ms, "photons/s", total / ms * 1e3, dict(zip(oracle.STATS, h["stats"].tolist())))
+    b = rt3d.to_host(rt3d.trace_batched(dm, wl.sza, wl.azimuth, wl.photons, 1, brick=wl.brick))
+    for k in ("abs_dir", "sfc_dif", "ledger", "stats"):
+        assert np.array_equal(h[k], b[k]), k
+
+
+def test_autotuner_picks_valid_options(rt3d, tmp_path):
+    from paper_2208_05247_amd import autotune
+    wl = syn.small_cumulus()
+    df = rt3d.DeviceFields.from_host(wl.fields)
+    res = autotune.tune_trace(df, wl.sza, wl.azimuth, sample=1 << 18, cache_path=str(tmp_path / "c.json"),
+                              bricks=[(4, 4, 4), (8, 8, 8)], walks=[0, 2], pools=[256, 1024])
+    assert res.table and res.ms_per_photon > 0
+    again = autotune.tune_trace(df, wl.sza, wl.azimuth, sample=1 << 18, cache_path=str(tmp_path / "c.json"))
+    assert again.cached and again.options == res.options
+    ref = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 16, 3, brick=res.options["brick"]))
+    got = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 16, 3, **res.options))
+    assert np.array_equal(ref["abs_dir"], got["abs_dir"])

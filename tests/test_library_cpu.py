@@ -62,7 +62,13 @@ def test_workspace_size_host_only(lib):
     g = Grid(256, 256, 128, 50.0, 50.0, 25.0)
     o = rt3d.options(brick=(8, 8, 8))
     n = rt3d.workspace_size(g, o)
-    assert n == 256 + 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16  # control, majorants, packed cells
+    # control block, photon ranges + column offsets, majorants, packed cells
+    assert n == 256 + 256 + 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16
+    nb = rt3d.workspace_size_batched(g, 112, o)
+    meta = (8 * (2 * 112 + 1) + 255) // 256 * 256
+    assert nb == 256 + meta + 112 * 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16 + 112 * 128 * 8 + 128 * 32 * 32 * 4
+    assert lib.rt3d_workspace_size_batched(ctypes.byref(rt3d.grid_struct(g)), 0, ctypes.byref(o)) == 0
+    assert lib.rt3d_workspace_size_batched(ctypes.byref(rt3d.grid_struct(g)), 257, ctypes.byref(o)) == 0
     bad = rt3d.options(brick=(3, 8, 8))
     with pytest.raises(rt3d.Rt3dError):
         rt3d.workspace_size(g, bad)

@@ -55,6 +55,32 @@ def measured_traffic(brick, photons):
     return float(fields["traffic_bytes_per_launch"])
 
 
+TTR_SOURCES = ("paper_2208_05247_amd/csrc/rt3d.hip", "paper_2208_05247_amd/csrc/denoise.hip",
+               "paper_2208_05247_amd/denoise.py", "paper_2208_05247_amd/experiment.py")
+
+
+def sources_hash(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_to_5pct():
+    """Plain vs batched+denoised time to a 5 % heating-rate RMS error, from
+    the committed summary of `python -m paper_2208_05247_amd.experiment`
+    (minutes of training and tracing, too long for the default bench run);
+    None unless it was measured with the current sources."""
+    prof = os.path.join(ROOT, "profiles", "time_to_5pct_batched_cumulus_1024x1024x128.md")
+    if not os.path.exists(prof):
+        return None
+    txt = open(prof).read()
+    if "    sources_sha256_16: " + sources_hash(TTR_SOURCES) not in txt or "```json" not in txt:
+        return None
+    return json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+
+
 def cpu_baseline(wl, target_s: float = 12.0) -> dict:
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -225,6 +251,7 @@ def main():
     }
     if not args.no_batched:
         res["batched"] = batched_measurement(max(1, min(args.steps, 3)))
+    res["time_to_5pct_heating_rms"] = time_to_5pct()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(res), flush=True)

@@ -1,0 +1,116 @@
+/*
+ * rt3d_denoise.h -- C ABI of the learned heating-rate denoiser kernels.
+ *
+ * The paper's convergence study (sec. 2.4 and sec. 3.2, figure 2) shows the
+ * Monte Carlo error falling as N_sample^-1/2 while the cost grows linearly
+ * in N_sample.  This library adds a small 3D convolutional encoder-decoder
+ * that maps low-photon heating tallies (plus the extinction field) to
+ * high-photon ones; it is trained on tally pairs produced by the tracer
+ * itself, and plain high-photon tracing remains the reference that judges
+ * its error.  Not part of the paper's method.
+ *
+ * Conventions (all pointers are DEVICE pointers owned by the caller; every
+ * call is asynchronous on `stream`, a hipStream_t passed as void*):
+ *   activations  BF16 (uint16 bits) channels-last [D][H][W][C], C a multiple
+ *                of 16;
+ *   weights      BF16 [Cout][k^3][Cin] (k = 1 or 3), Cout a multiple of 32;
+ *                FP32 master copies, gradients and Adam moments of the same
+ *                shape; biases FP32 [Cout];
+ *   convolution  stride 1, zero padding k/2, FP32 accumulation on the matrix
+ *                cores (v_mfma_f32_32x32x16_bf16), BF16 output rounding to
+ *                nearest even.
+ * Errors: RT3D_EINVAL for bad arguments (checked before any launch),
+ * RT3D_EDEVICE for a HIP failure (text in rt3d_dn_last_error()).
+ */
+#ifndef RT3D_DENOISE_H
+#define RT3D_DENOISE_H
+
+#include <stdint.h>
+
+#include "rt3d.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Shape of one convolution: grid D x H x W, inputs c1 channels from x1 and
+ * c2 (possibly 0) from x2, concatenated in that order; cout outputs. */
+typedef struct {
+    int32_t D, H, W;
+    int32_t c1, c2, cout;
+    int32_t ksize; /* 1 or 3 */
+} rt3d_dn_conv;
+
+const char* rt3d_dn_last_error(void);
+
+/* y = act(conv(concat(x1, x2), w) + bias); act = ReLU if relu != 0.
+ * Output channels [0, o1) go to y1 ([vox][o1]), [o1, cout) to y2
+ * ([vox][cout - o1], o1 a multiple of 32).  If yf is not NULL the FP32
+ * values are also written to yf [vox][cout] (y1 may then be NULL when
+ * o1 == cout).  bias may be NULL.  With flipped weights (rt3d_dn_flip_weights)
+ * and no bias/activation this computes the data gradient. */
+rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* w,
+                               const float* bias, int32_t relu, uint16_t* y1, uint16_t* y2, int32_t o1, float* yf,
+                               void* stream);
+
+/* wt[ci][k^3 - 1 - t][co] = w[co][t][ci]: the kernel of the data gradient. */
+rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, int32_t cin, int32_t ksize,
+                                 void* stream);
+
+/* dw[co][t][ci] += sum_v dz[v][co] x[v + offset(t)][ci] (FP32, accumulated
+ * with atomics: clear dw first); db[co] += sum_v dz[v][co] if db != NULL.
+ * x = concat(x1, x2) is the forward input, dz the gradient at the
+ * convolution output (after the activation's derivative). */
+rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
+                                 float* dw, float* db, void* stream);
+
+/* dz = dy where y > 0 else 0 (ReLU derivative through its output y). */
+rt3d_status rt3d_dn_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dz, uint64_t n, void* stream);
+
+/* out = a + b elementwise (BF16). */
+rt3d_status rt3d_dn_add(const uint16_t* a, const uint16_t* b, uint16_t* out, uint64_t n, void* stream);
+
+/* 2x2x2 average pooling of x [D][H][W][C] into y [D/2][H/2][W/2][C]; with
+ * backward != 0, x is the gradient at the pooled output and y receives the
+ * gradient at the input (each input voxel gets 1/8 of its parent's). */
+rt3d_status rt3d_dn_pool2(const uint16_t* x, uint16_t* y, int32_t D, int32_t H, int32_t W, int32_t C,
+                          int32_t backward, void* stream);
+
+/* Nearest-neighbour 2x upsampling of x [D][H][W][C] into y [2D][2H][2W][C];
+ * with backward != 0, x is the gradient at the upsampled output
+ * ([2D][2H][2W][C]) and y [D][H][W][C] receives the sum over children. */
+rt3d_status rt3d_dn_up2(const uint16_t* x, uint16_t* y, int32_t D, int32_t H, int32_t W, int32_t C,
+                        int32_t backward, void* stream);
+
+/* Residual head and squared-error loss: pred[v][c] = out[v][c] + base[v][c]
+ * for c < nout (out is FP32 [vox][cpad], base/target/pred FP32 [vox][nout]);
+ * if target != NULL: *loss += sum (pred - target)^2 (FP64) and dout[v][c] =
+ * 2 (pred - target) / (nvox nout) (BF16 [vox][cpad], 0 in padding).  pred,
+ * dout, loss may be NULL. */
+rt3d_status rt3d_dn_mse(const float* out, int32_t cpad, const float* base, const float* target, int32_t nout,
+                        uint64_t nvox, float* pred, uint16_t* dout, double* loss, void* stream);
+
+/* One Adam step (Kingma and Ba) on n FP32 parameters p with gradient g and
+ * moments m1, m2; step counts from 1; pb (may be NULL) receives BF16 p. */
+rt3d_status rt3d_dn_adam(float* p, const float* g, float* m1, float* m2, uint16_t* pb, uint64_t n, float lr,
+                         float b1, float b2, float eps, int32_t step, void* stream);
+
+/* y = BF16(x). */
+rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* stream);
+
+/* Network input per voxel: channel 0 = hdir/scale, 1 = hdif/scale,
+ * 2 = ln(1 + 20 k_ext dz), channels 3..cpad-1 = 0 (feat BF16 [vox][cpad]);
+ * base FP32 [vox][2] = (hdir/scale, hdif/scale), the residual the network
+ * corrects.  hdir, hdif: FP32 heating fields; k_ext FP32 [vox]. */
+rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, float dz, float scale,
+                             uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream);
+
+/* hdir[v] = max(pred[v][0], 0) scale, hdif[v] = max(pred[v][1], 0) scale. */
+rt3d_status rt3d_dn_unfeature(const float* pred, float scale, uint64_t nvox, float* hdir, float* hdif,
+                              void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT3D_DENOISE_H */

@@ -1,0 +1,544 @@
+// denoise.hip -- BF16 MFMA kernels of the learned heating-rate denoiser:
+// a 3D convolutional encoder-decoder trained on low/high-photon tally pairs
+// produced by the tracer.  Declared in include/rt3d_denoise.h.
+//
+// Conventions: activations are BF16 channels-last [D][H][W][C] (C a multiple
+// of 16); weights BF16 [Cout][KS^3][Cin] with FP32 master copies; all
+// products accumulate in FP32 on the matrix cores.
+//
+// Convolution = implicit GEMM on v_mfma_f32_32x32x16_bf16: one wave owns 32
+// consecutive voxels along x (the GEMM rows) and 32 output channels (the
+// columns); the reduction runs over the KS^3 taps and 16-channel chunks.  A
+// lane feeds the A operand with 8 channels of one voxel (one 16-byte load,
+// zero outside the domain) and the B operand with 8 input channels of one
+// output channel's weights.  The accumulator of lane l, element r holds row
+// 8*(r/4) + 4*(l/32) + r%4, column l%32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "rt3d.h"
+#include "rt3d_denoise.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+thread_local char d_err[256] = "";
+
+rt3d_status dfail(hipError_t e, const char* where) {
+    snprintf(d_err, sizeof d_err, "%s: %s", where, hipGetErrorString(e));
+    return RT3D_EDEVICE;
+}
+
+#define DN_TRY(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return dfail(e_, #expr); \
+    } while (0)
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// FP32 -> BF16, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+unsigned blocks_for(size_t n, unsigned threads = 256, unsigned cap = 65535) {
+    size_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// Convolution forward (also the data gradient, with flipped weights)
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const uint16_t* x1;
+    const uint16_t* x2;
+    int c1, c2;            // input channels from x1 and x2 (multiples of 16)
+    const uint16_t* w;     // [cout][taps][c1 + c2]
+    const float* bias;     // [cout] or null
+    uint16_t* y1;          // channels [0, o1)
+    uint16_t* y2;          // channels [o1, cout)
+    int o1;
+    float* yf;             // optional FP32 copy [vox][cout]
+    int D, H, W, cout, relu;
+};
+
+template <int KS>
+__global__ void __launch_bounds__(256) conv_fwd_kernel(const ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ntco = a.cout / 32;
+    const int tiles_x = (a.W + 31) / 32;
+    const long ntiles = (long)a.D * a.H * tiles_x * ntco;
+    if (wave >= ntiles) return;
+    const int cot = (int)(wave % ntco);
+    long rest = wave / ntco;
+    const int tx = (int)(rest % tiles_x);
+    rest /= tiles_x;
+    const int yy = (int)(rest % a.H);
+    const int zz = (int)(rest / a.H);
+    const int m = lane & 31, half = lane >> 5;
+    const int xv = tx * 32 + m;
+    const int co = cot * 32 + m;
+    const int cin = a.c1 + a.c2;
+    constexpr int taps = KS * KS * KS;
+    f32x16 acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int t = 0; t < taps; ++t) {
+        const int dz = t / (KS * KS) - KS / 2, dy = (t / KS) % KS - KS / 2, dx = t % KS - KS / 2;
+        const int z = zz + dz, y = yy + dy, x = xv + dx;
+        const bool inb = z >= 0 && z < a.D && y >= 0 && y < a.H && x >= 0 && x < a.W;
+        const long vox = ((long)z * a.H + y) * a.W + x;
+        const uint16_t* wrow = a.w + ((long)co * taps + t) * cin + 8 * half;
+        for (int c0 = 0; c0 < cin; c0 += 16) {
+            uint4 av = make_uint4(0u, 0u, 0u, 0u);
+            if (inb) {
+                const uint16_t* src = c0 < a.c1 ? a.x1 + vox * a.c1 + c0 : a.x2 + vox * a.c2 + (c0 - a.c1);
+                av = *(const uint4*)(src + 8 * half);
+            }
+            const uint4 bv = *(const uint4*)(wrow + c0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
+        }
+    }
+    const int n = cot * 32 + m;
+    const float b = a.bias ? a.bias[n] : 0.0f;
+    for (int r = 0; r < 16; ++r) {
+        const int mm = 8 * (r >> 2) + 4 * half + (r & 3);
+        const int x = tx * 32 + mm;
+        if (x >= a.W) continue;
+        float v = acc[r] + b;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        const long vox = ((long)zz * a.H + yy) * a.W + x;
+        if (a.yf) a.yf[vox * a.cout + n] = v;
+        if (n < a.o1) {
+            if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
+        } else if (a.y2) {
+            a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+        }
+    }
+}
+
+// wt[ci][taps-1-t][co] = w[co][t][ci]  (data gradient = convolution of the
+// output gradient with the flipped, transposed kernel)
+__global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int cout, int cin,
+                                    int taps) {
+    const size_t n = (size_t)cout * cin * taps;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % cin);
+        const int t = (int)((i / cin) % taps);
+        const int co = (int)(i / ((size_t)cin * taps));
+        wt[((size_t)ci * taps + (taps - 1 - t)) * cout + co] = w[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dw[co][t][ci] += sum_v dz[v][co] x[v + off(t)][ci]
+// GEMM rows = output channels, columns = input channels, reduction over 16
+// voxels of one x-row per MFMA.  One wave: (co tile, ci tile, tap, rows).
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+    const uint16_t* dz;
+    int cout;
+    const uint16_t* x1;
+    const uint16_t* x2;
+    int c1, c2;
+    float* dw;
+    int D, H, W, rows_per_wave;
+};
+
+template <int KS>
+__global__ void __launch_bounds__(256) conv_wgrad_kernel(const WgradArgs a) {
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr int taps = KS * KS * KS;
+    const int cin = a.c1 + a.c2;
+    const int ntco = a.cout / 32, ntci = (cin + 31) / 32;
+    const long nrows = (long)a.D * a.H;
+    const long nchunks = (nrows + a.rows_per_wave - 1) / a.rows_per_wave;
+    const long ntasks = (long)ntco * ntci * taps * nchunks;
+    if (wave >= ntasks) return;
+    const int cot = (int)(wave % ntco);
+    long rest = wave / ntco;
+    const int cit = (int)(rest % ntci);
+    rest /= ntci;
+    const int t = (int)(rest % taps);
+    const long chunk = rest / taps;
+    const int dz = t / (KS * KS) - KS / 2, dy = (t / KS) % KS - KS / 2, dx = t % KS - KS / 2;
+    const int m = lane & 31, half = lane >> 5;
+    const int co = cot * 32 + m;
+    const int ci = cit * 32 + m;
+    const bool ci_ok = ci < cin;
+    const uint16_t* xs = ci < a.c1 ? a.x1 : a.x2;
+    const int xc = ci < a.c1 ? a.c1 : a.c2;
+    const int xci = ci < a.c1 ? ci : ci - a.c1;
+    f32x16 acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const long r0 = chunk * a.rows_per_wave;
+    const long r1 = r0 + a.rows_per_wave < nrows ? r0 + a.rows_per_wave : nrows;
+    for (long row = r0; row < r1; ++row) {
+        const int zz = (int)(row / a.H), yy = (int)(row % a.H);
+        const int z = zz + dz, y = yy + dy;
+        const bool row_ok = z >= 0 && z < a.D && y >= 0 && y < a.H;
+        const long vrow = row * a.W;                    // first voxel of the output row
+        const long srow = ((long)z * a.H + y) * a.W;    // first voxel of the shifted input row
+        for (int x0 = 0; x0 < a.W; x0 += 16) {
+            bf16x8 av, bv;
+            for (int i = 0; i < 8; ++i) {
+                const int x = x0 + 8 * half + i;
+                const bool xin = x < a.W;
+                const uint16_t g = xin ? a.dz[(vrow + x) * a.cout + co] : (uint16_t)0;
+                const int xs_ = x + dx;
+                const bool sin = row_ok && xin && ci_ok && xs_ >= 0 && xs_ < a.W;
+                const uint16_t v = sin ? xs[(srow + xs_) * xc + xci] : (uint16_t)0;
+                av[i] = __builtin_bit_cast(__bf16, g);
+                bv[i] = __builtin_bit_cast(__bf16, v);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    const int n = cit * 32 + m;  // input channel (column)
+    if (n < cin) {
+        for (int r = 0; r < 16; ++r) {
+            const int mm = cot * 32 + 8 * (r >> 2) + 4 * half + (r & 3);  // output channel (row)
+            atomicAdd(&a.dw[((long)mm * taps + t) * cin + n], acc[r]);
+        }
+    }
+}
+
+// db[c] += sum over voxels of dz[v][c]
+__global__ void bias_grad_kernel(const uint16_t* __restrict__ dz, float* __restrict__ db, size_t nvox, int c) {
+    __shared__ float part[256];
+    const int ch = blockIdx.y;
+    float s = 0.0f;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x)
+        s += bf2f(dz[v * c + ch]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&db[ch], part[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and resampling kernels (BF16 storage, FP32 arithmetic)
+// ---------------------------------------------------------------------------
+__global__ void relu_bwd_kernel(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ y,
+                                uint16_t* __restrict__ dz, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dz[i] = bf2f(y[i]) > 0.0f ? dy[i] : (uint16_t)0;
+}
+
+__global__ void add_kernel(const uint16_t* __restrict__ a, const uint16_t* __restrict__ b, uint16_t* __restrict__ out,
+                           size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+}
+
+// 2x2x2 average pooling: out [D/2][H/2][W/2][C]
+__global__ void pool2_kernel(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int D, int H, int W, int C) {
+    const int d = D / 2, h = H / 2, w = W / 2;
+    const size_t n = (size_t)d * h * w * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        size_t v = i / C;
+        const int xo = (int)(v % w), yo = (int)((v / w) % h), zo = (int)(v / ((size_t)w * h));
+        float s = 0.0f;
+        for (int q = 0; q < 8; ++q) {
+            const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
+            s += bf2f(x[(((size_t)z * H + yy) * W + xx) * C + c]);
+        }
+        y[i] = f2bf(0.125f * s);
+    }
+}
+
+__global__ void pool2_bwd_kernel(const uint16_t* __restrict__ dy, uint16_t* __restrict__ dx, int D, int H, int W,
+                                 int C) {
+    const size_t n = (size_t)D * H * W * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((size_t)W * H));
+        dx[i] = f2bf(0.125f * bf2f(dy[((((size_t)(z / 2)) * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]));
+    }
+}
+
+// nearest-neighbour 2x upsampling: out [2D][2H][2W][C]
+__global__ void up2_kernel(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int D, int H, int W, int C) {
+    const size_t n = (size_t)8 * D * H * W * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        const int W2 = 2 * W, H2 = 2 * H;
+        const int xx = (int)(v % W2), yy = (int)((v / W2) % H2), zz = (int)(v / ((size_t)W2 * H2));
+        y[i] = x[((((size_t)(zz / 2)) * H + yy / 2) * W + xx / 2) * C + c];
+    }
+}
+
+__global__ void up2_bwd_kernel(const uint16_t* __restrict__ dy, uint16_t* __restrict__ dx, int D, int H, int W,
+                               int C) {
+    const size_t n = (size_t)D * H * W * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t v = i / C;
+        const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((size_t)W * H));
+        float s = 0.0f;
+        for (int q = 0; q < 8; ++q) {
+            const int zz = 2 * z + (q >> 2), yy = 2 * y + ((q >> 1) & 1), xx = 2 * x + (q & 1);
+            s += bf2f(dy[(((size_t)zz * (2 * H) + yy) * (2 * W) + xx) * C + c]);
+        }
+        dx[i] = f2bf(s);
+    }
+}
+
+// Residual output head and loss: pred[v][c] = out[v][c] + base[v][c] for the
+// first nout channels of the FP32 network output (cpad channels per voxel);
+// loss += sum (pred - target)^2 (FP64 accumulation); dout[v][c] =
+// 2 (pred - target) / count as BF16 (0 for padding channels).
+__global__ void mse_kernel(const float* __restrict__ out, int cpad, const float* __restrict__ base,
+                           const float* __restrict__ target, int nout, size_t nvox, double inv_count,
+                           float* __restrict__ pred, uint16_t* __restrict__ dout, double* __restrict__ loss) {
+    __shared__ double part[256];
+    double s = 0.0;
+    const size_t n = nvox * cpad;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % cpad);
+        const size_t v = i / cpad;
+        float g = 0.0f;
+        if (c < nout) {
+            const float p = out[i] + base[v * nout + c];
+            if (pred) pred[v * nout + c] = p;
+            if (target) {
+                const float d = p - target[v * nout + c];
+                s += (double)d * d;
+                g = (float)(2.0 * inv_count) * d;
+            }
+        }
+        if (dout) dout[i] = f2bf(g);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) atomicAdd(loss, part[0]);
+}
+
+// Adam on FP32 master parameters, BF16 copy for the forward pass.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                            float* __restrict__ m2, uint16_t* __restrict__ pb, size_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float a = b1 * m1[i] + (1.0f - b1) * gi;
+        const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
+        m1[i] = a;
+        m2[i] = b;
+        const float v = p[i] - lr * (a * c1) / (sqrtf(b * c2) + eps);
+        p[i] = v;
+        if (pb) pb[i] = f2bf(v);
+    }
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = f2bf(x[i]);
+}
+
+// Input features per voxel: scaled direct and diffuse heating, log optical
+// thickness of the cell, zero padding to cpad channels (BF16); the scaled
+// heating is also written as the FP32 residual base [v][2].
+__global__ void features_kernel(const float* __restrict__ hdir, const float* __restrict__ hdif,
+                                const float* __restrict__ k_ext, float dz, float inv_scale, size_t nvox, int cpad,
+                                uint16_t* __restrict__ feat, float* __restrict__ base) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        const float a = hdir[v] * inv_scale, b = hdif[v] * inv_scale;
+        const float c = __logf(1.0f + 20.0f * k_ext[v] * dz);
+        uint16_t* f = feat + v * cpad;
+        f[0] = f2bf(a);
+        f[1] = f2bf(b);
+        f[2] = f2bf(c);
+        for (int q = 3; q < cpad; ++q) f[q] = 0;
+        base[2 * v] = a;
+        base[2 * v + 1] = b;
+    }
+}
+
+// Split a [v][2] prediction back into heating fields, times scale, >= 0.
+__global__ void unfeature_kernel(const float* __restrict__ pred, float scale, size_t nvox, float* __restrict__ hdir,
+                                 float* __restrict__ hdif) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        hdir[v] = fmaxf(pred[2 * v], 0.0f) * scale;
+        hdif[v] = fmaxf(pred[2 * v + 1], 0.0f) * scale;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI (include/rt3d_denoise.h)
+// ===========================================================================
+extern "C" {
+
+const char* rt3d_dn_last_error(void) { return d_err; }
+
+rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* w,
+                               const float* bias, int32_t relu, uint16_t* y1, uint16_t* y2, int32_t o1, float* yf,
+                               void* stream) {
+    if (!c || !x1 || !w || (c->c2 > 0 && !x2) || (!y1 && !yf)) return RT3D_EINVAL;
+    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return RT3D_EINVAL;
+    if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
+    if (o1 <= 0 || o1 > c->cout || o1 % 32 || (o1 < c->cout && !y2)) return RT3D_EINVAL;
+    ConvArgs a;
+    a.x1 = x1; a.x2 = x2; a.c1 = c->c1; a.c2 = c->c2; a.w = w; a.bias = bias;
+    a.y1 = y1; a.y2 = y2; a.o1 = o1; a.yf = yf;
+    a.D = c->D; a.H = c->H; a.W = c->W; a.cout = c->cout; a.relu = relu ? 1 : 0;
+    const long waves = (long)c->D * c->H * ((c->W + 31) / 32) * (c->cout / 32);
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (c->ksize == 3)
+        hipLaunchKernelGGL(conv_fwd_kernel<3>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, int32_t cin, int32_t ksize,
+                                 void* stream) {
+    if (!w || !wt || cout <= 0 || cin <= 0 || (ksize != 1 && ksize != 3)) return RT3D_EINVAL;
+    const int taps = ksize * ksize * ksize;
+    hipLaunchKernelGGL(flip_weights_kernel, dim3(blocks_for((size_t)cout * cin * taps)), dim3(256), 0,
+                       (hipStream_t)stream, w, wt, cout, cin, taps);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
+                                 float* dw, float* db, void* stream) {
+    if (!c || !x1 || !dz || !dw || (c->c2 > 0 && !x2)) return RT3D_EINVAL;
+    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return RT3D_EINVAL;
+    if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
+    WgradArgs a;
+    a.dz = dz; a.cout = c->cout; a.x1 = x1; a.x2 = x2; a.c1 = c->c1; a.c2 = c->c2; a.dw = dw;
+    a.D = c->D; a.H = c->H; a.W = c->W;
+    const int taps = c->ksize * c->ksize * c->ksize;
+    const long base_tasks = (long)(c->cout / 32) * ((c->c1 + c->c2 + 31) / 32) * taps;
+    const long nrows = (long)c->D * c->H;
+    // about 4096 waves in flight, at least one row each
+    long chunks = 4096 / base_tasks;
+    if (chunks < 1) chunks = 1;
+    if (chunks > nrows) chunks = nrows;
+    a.rows_per_wave = (int)((nrows + chunks - 1) / chunks);
+    const long waves = base_tasks * ((nrows + a.rows_per_wave - 1) / a.rows_per_wave);
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    hipStream_t st = (hipStream_t)stream;
+    if (c->ksize == 3)
+        hipLaunchKernelGGL(conv_wgrad_kernel<3>, dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(conv_wgrad_kernel<1>, dim3(blocks), dim3(256), 0, st, a);
+    DN_TRY(hipGetLastError());
+    if (db) {
+        const size_t nvox = (size_t)c->D * c->H * c->W;
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(nvox, 256, 256), c->cout), dim3(256), 0, st, dz, db,
+                           nvox, c->cout);
+        DN_TRY(hipGetLastError());
+    }
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dz, uint64_t n, void* stream) {
+    if (!dy || !y || !dz) return RT3D_EINVAL;
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, dy, y, dz, (size_t)n);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_add(const uint16_t* a, const uint16_t* b, uint16_t* out, uint64_t n, void* stream) {
+    if (!a || !b || !out) return RT3D_EINVAL;
+    hipLaunchKernelGGL(add_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, a, b, out, (size_t)n);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_pool2(const uint16_t* x, uint16_t* y, int32_t D, int32_t H, int32_t W, int32_t C, int32_t backward,
+                          void* stream) {
+    if (!x || !y || D <= 0 || H <= 0 || W <= 0 || C <= 0 || D % 2 || H % 2 || W % 2) return RT3D_EINVAL;
+    const size_t n = (size_t)D * H * W * C;
+    if (backward)
+        hipLaunchKernelGGL(pool2_bwd_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
+    else
+        hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(n / 8)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_up2(const uint16_t* x, uint16_t* y, int32_t D, int32_t H, int32_t W, int32_t C, int32_t backward,
+                        void* stream) {
+    if (!x || !y || D <= 0 || H <= 0 || W <= 0 || C <= 0) return RT3D_EINVAL;
+    const size_t n = (size_t)D * H * W * C;
+    if (backward)
+        hipLaunchKernelGGL(up2_bwd_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
+    else
+        hipLaunchKernelGGL(up2_kernel, dim3(blocks_for(8 * n)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_mse(const float* out, int32_t cpad, const float* base, const float* target, int32_t nout,
+                        uint64_t nvox, float* pred, uint16_t* dout, double* loss, void* stream) {
+    if (!out || !base || cpad <= 0 || nout <= 0 || nout > cpad || nvox == 0) return RT3D_EINVAL;
+    if ((dout || loss) && !target) return RT3D_EINVAL;
+    const double inv = 1.0 / ((double)nvox * nout);
+    hipLaunchKernelGGL(mse_kernel, dim3(blocks_for((size_t)nvox * cpad, 256, 4096)), dim3(256), 0,
+                       (hipStream_t)stream, out, cpad, base, target, nout, (size_t)nvox, inv, pred, dout, loss);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_adam(float* p, const float* g, float* m1, float* m2, uint16_t* pb, uint64_t n, float lr, float b1,
+                         float b2, float eps, int32_t step, void* stream) {
+    if (!p || !g || !m1 || !m2 || step < 1) return RT3D_EINVAL;
+    const float c1 = 1.0f / (1.0f - powf(b1, (float)step)), c2 = 1.0f / (1.0f - powf(b2, (float)step));
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, p, g, m1, m2, pb,
+                       (size_t)n, lr, b1, b2, eps, c1, c2);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* stream) {
+    if (!x || !y) return RT3D_EINVAL;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, x, y, (size_t)n);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, float dz, float scale,
+                             uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream) {
+    if (!hdir || !hdif || !k_ext || !feat || !base || cpad < 16 || cpad % 16 || !(scale > 0.0f)) return RT3D_EINVAL;
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, hdir, hdif, k_ext,
+                       dz, 1.0f / scale, (size_t)nvox, cpad, feat, base);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_unfeature(const float* pred, float scale, uint64_t nvox, float* hdir, float* hdif,
+                              void* stream) {
+    if (!pred || !hdir || !hdif) return RT3D_EINVAL;
+    hipLaunchKernelGGL(unfeature_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, pred, scale,
+                       (size_t)nvox, hdir, hdif);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,366 @@
+"""Learned heating-rate denoiser: binding of include/rt3d_denoise.h and the
+encoder-decoder built from its kernels.
+
+Network (4 resolution levels, 32 base channels, BF16 weights and
+activations, FP32 accumulation on the matrix cores):
+
+  x0 [16: hdir/s, hdif/s, ln(1+20 k_ext dz), 0...]
+  e0 = relu(conv3 x0 -> 32)           level 0
+  e1 = relu(conv3 pool(e0) -> 64)     level 1
+  e2 = relu(conv3 pool(e1) -> 128)    level 2
+  b  = relu(conv3 pool(e2) -> 256)    level 3
+  d2 = relu(conv3 [up(b), e2] -> 128)
+  d1 = relu(conv3 [up(d2), e1] -> 64)
+  d0 = relu(conv3 [up(d1), e0] -> 32)
+  out = conv1 d0 -> 32 (FP32; channels 0, 1 used)
+  prediction = out[:, :2] + (hdir/s, hdif/s)      (residual correction)
+
+s is the mean of the noisy heating over the field (known at inference).
+Every step runs in the HIP kernels; PyTorch only allocates memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import rt3d
+
+CPAD = 16          # input feature channels (3 used)
+HEAD = 32          # head output channels (2 used)
+NOUT = 2
+LEVELS = 4
+
+
+class _Conv(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("c1", ctypes.c_int32), ("c2", ctypes.c_int32), ("cout", ctypes.c_int32),
+                ("ksize", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    lib = rt3d.load()
+    P, I, U = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+    sig = {
+        "rt3d_dn_conv3d_fwd": [ctypes.POINTER(_Conv), P, P, P, P, I, P, P, I, P, P],
+        "rt3d_dn_flip_weights": [P, P, I, I, I, P],
+        "rt3d_dn_conv3d_wgrad": [ctypes.POINTER(_Conv), P, P, P, P, P, P],
+        "rt3d_dn_relu_bwd": [P, P, P, U, P],
+        "rt3d_dn_add": [P, P, P, U, P],
+        "rt3d_dn_pool2": [P, P, I, I, I, I, I, P],
+        "rt3d_dn_up2": [P, P, I, I, I, I, I, P],
+        "rt3d_dn_mse": [P, I, P, P, I, U, P, P, P, P],
+        "rt3d_dn_adam": [P, P, P, P, P, U, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, I, P],
+        "rt3d_dn_to_bf16": [P, P, U, P],
+        "rt3d_dn_features": [P, P, P, ctypes.c_float, ctypes.c_float, U, I, P, P, P],
+        "rt3d_dn_unfeature": [P, ctypes.c_float, U, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.rt3d_dn_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+EXPORTS = ("rt3d_dn_last_error", "rt3d_dn_conv3d_fwd", "rt3d_dn_flip_weights", "rt3d_dn_conv3d_wgrad",
+           "rt3d_dn_relu_bwd", "rt3d_dn_add", "rt3d_dn_pool2", "rt3d_dn_up2", "rt3d_dn_mse", "rt3d_dn_adam",
+           "rt3d_dn_to_bf16", "rt3d_dn_features", "rt3d_dn_unfeature")
+
+
+def _p(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _s():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(st, what):
+    if st != 0:
+        detail = load().rt3d_dn_last_error().decode() if st == rt3d.EDEVICE else ""
+        raise rt3d.Rt3dError(st, what, detail)
+
+
+def bf16_empty(*shape, device="cuda"):
+    """BF16 storage as torch.bfloat16 (the kernels read the raw bits)."""
+    return torch.empty(*shape, dtype=torch.bfloat16, device=device)
+
+
+# ---------------------------------------------------------------------------
+# Kernel wrappers
+# ---------------------------------------------------------------------------
+
+def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=None):
+    D, H, W, c1 = x1.shape
+    c2 = 0 if x2 is None else x2.shape[3]
+    o1 = cout if o1 is None else o1
+    c = _Conv(D, H, W, c1, c2, cout, ksize)
+    _check(load().rt3d_dn_conv3d_fwd(ctypes.byref(c), _p(x1), _p(x2), _p(w), _p(bias), int(relu), _p(y1), _p(y2),
+                                     int(o1), _p(yf), _s()), "rt3d_dn_conv3d_fwd")
+
+
+def flip(w, cout, cin, ksize, out):
+    _check(load().rt3d_dn_flip_weights(_p(w), _p(out), cout, cin, ksize, _s()), "rt3d_dn_flip_weights")
+
+
+def conv_wgrad(x1, x2, dz, cout, ksize, dw, db):
+    D, H, W, c1 = x1.shape
+    c2 = 0 if x2 is None else x2.shape[3]
+    c = _Conv(D, H, W, c1, c2, cout, ksize)
+    _check(load().rt3d_dn_conv3d_wgrad(ctypes.byref(c), _p(x1), _p(x2), _p(dz), _p(dw), _p(db), _s()),
+           "rt3d_dn_conv3d_wgrad")
+
+
+def relu_bwd(dy, y, out):
+    _check(load().rt3d_dn_relu_bwd(_p(dy), _p(y), _p(out), dy.numel(), _s()), "rt3d_dn_relu_bwd")
+
+
+def add(a, b, out):
+    _check(load().rt3d_dn_add(_p(a), _p(b), _p(out), a.numel(), _s()), "rt3d_dn_add")
+
+
+def pool2(x, backward=False, out=None):
+    if not backward:
+        D, H, W, C = x.shape
+        out = bf16_empty(D // 2, H // 2, W // 2, C) if out is None else out
+    else:
+        D, H, W, C = out.shape
+    _check(load().rt3d_dn_pool2(_p(x), _p(out), D, H, W, C, int(backward), _s()), "rt3d_dn_pool2")
+    return out
+
+
+def up2(x, backward=False, out=None):
+    if not backward:
+        D, H, W, C = x.shape
+        out = bf16_empty(2 * D, 2 * H, 2 * W, C) if out is None else out
+    else:
+        D, H, W, C = out.shape
+    _check(load().rt3d_dn_up2(_p(x), _p(out), D, H, W, C, int(backward), _s()), "rt3d_dn_up2")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Network
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Layer:
+    name: str
+    c1: int
+    c2: int
+    cout: int
+    ksize: int
+    relu: bool
+
+
+def architecture(base: int = 32) -> List[Layer]:
+    c0, c1, c2, c3 = base, 2 * base, 4 * base, 8 * base
+    return [Layer("e0", CPAD, 0, c0, 3, True), Layer("e1", c0, 0, c1, 3, True),
+            Layer("e2", c1, 0, c2, 3, True), Layer("b", c2, 0, c3, 3, True),
+            Layer("d2", c3, c2, c2, 3, True), Layer("d1", c2, c1, c1, 3, True),
+            Layer("d0", c1, c0, c0, 3, True), Layer("head", c0, 0, HEAD, 1, False)]
+
+
+class Denoiser:
+    """Parameters (FP32 masters, BF16 copies, gradients, Adam moments) and the
+    forward / backward passes over one field."""
+
+    def __init__(self, base: int = 32, seed: int = 0, device="cuda"):
+        self.layers = architecture(base)
+        self.device = device
+        g = torch.Generator().manual_seed(seed)
+        self.p, self.pb, self.g, self.m1, self.m2 = {}, {}, {}, {}, {}
+        self.bias, self.gbias, self.mb1, self.mb2 = {}, {}, {}, {}
+        for L in self.layers:
+            taps = L.ksize ** 3
+            fan_in = taps * (L.c1 + L.c2)
+            std = math.sqrt(2.0 / fan_in) if L.name != "head" else 1e-3
+            w = torch.randn(L.cout, taps, L.c1 + L.c2, generator=g, dtype=torch.float32) * std
+            if L.name == "e0":
+                w[:, :, 3:] = 0.0  # padding channels carry nothing
+            if L.name == "head":
+                w[NOUT:] = 0.0
+            self.p[L.name] = w.to(device).contiguous()
+            self.pb[L.name] = self.p[L.name].to(torch.bfloat16)
+            self.g[L.name] = torch.zeros_like(self.p[L.name])
+            self.m1[L.name] = torch.zeros_like(self.p[L.name])
+            self.m2[L.name] = torch.zeros_like(self.p[L.name])
+            self.bias[L.name] = torch.zeros(L.cout, dtype=torch.float32, device=device)
+            self.gbias[L.name] = torch.zeros_like(self.bias[L.name])
+            self.mb1[L.name] = torch.zeros_like(self.bias[L.name])
+            self.mb2[L.name] = torch.zeros_like(self.bias[L.name])
+        self.step_count = 0
+
+    def n_params(self) -> int:
+        return sum(v.numel() for v in self.p.values()) + sum(v.numel() for v in self.bias.values())
+
+    def state(self) -> Dict[str, torch.Tensor]:
+        return {**{f"w_{k}": v for k, v in self.p.items()}, **{f"b_{k}": v for k, v in self.bias.items()}}
+
+    def load_state(self, st: Dict[str, torch.Tensor]):
+        for k in self.p:
+            self.p[k].copy_(st[f"w_{k}"])
+            self.pb[k].copy_(self.p[k].to(torch.bfloat16))
+            self.bias[k].copy_(st[f"b_{k}"])
+
+    # -- forward ------------------------------------------------------------
+    def _conv(self, name, x1, x2=None, yf=None):
+        L = next(l for l in self.layers if l.name == name)
+        D, H, W, _ = x1.shape
+        y = None if yf is not None else bf16_empty(D, H, W, L.cout)
+        conv_fwd(x1, x2, self.pb[name], self.bias[name], L.relu, L.cout, L.ksize, y1=y, yf=yf)
+        return y
+
+    def forward(self, feat: torch.Tensor, keep: bool = False) -> torch.Tensor:
+        """feat: BF16 [D][H][W][16]; returns FP32 head output [D][H][W][32]."""
+        D, H, W, _ = feat.shape
+        if D % 8 or H % 8 or W % 8:
+            raise ValueError("grid dimensions must be multiples of 8 (three pooling levels)")
+        a = {"x0": feat}
+        a["e0"] = self._conv("e0", feat)
+        a["p0"] = pool2(a["e0"])
+        a["e1"] = self._conv("e1", a["p0"])
+        a["p1"] = pool2(a["e1"])
+        a["e2"] = self._conv("e2", a["p1"])
+        a["p2"] = pool2(a["e2"])
+        a["b"] = self._conv("b", a["p2"])
+        a["u2"] = up2(a["b"])
+        a["d2"] = self._conv("d2", a["u2"], a["e2"])
+        a["u1"] = up2(a["d2"])
+        a["d1"] = self._conv("d1", a["u1"], a["e1"])
+        a["u0"] = up2(a["d1"])
+        a["d0"] = self._conv("d0", a["u0"], a["e0"])
+        out = torch.empty(D, H, W, HEAD, dtype=torch.float32, device=feat.device)
+        self._conv("head", a["d0"], yf=out)
+        if keep:
+            self.acts = a
+        return out
+
+    # -- backward -----------------------------------------------------------
+    def _data_grad(self, name, dz, out1, out2=None):
+        L = next(l for l in self.layers if l.name == name)
+        cin = L.c1 + L.c2
+        wt = bf16_empty(cin, L.ksize ** 3, L.cout)
+        flip(self.pb[name], L.cout, cin, L.ksize, wt)
+        conv_fwd(dz, None, wt, None, False, cin, L.ksize, y1=out1, y2=out2, o1=L.c1)
+
+    def _wgrad(self, name, x1, x2, dz):
+        L = next(l for l in self.layers if l.name == name)
+        conv_wgrad(x1, x2, dz, L.cout, L.ksize, self.g[name], self.gbias[name])
+
+    def backward(self, dout: torch.Tensor):
+        """dout: BF16 [D][H][W][32] gradient at the head output.  Fills the
+        FP32 gradients (cleared first)."""
+        a = self.acts
+        for k in self.g:
+            self.g[k].zero_()
+            self.gbias[k].zero_()
+        like = lambda t: torch.empty_like(t)
+        self._wgrad("head", a["d0"], None, dout)
+        dd0 = like(a["d0"])
+        self._data_grad("head", dout, dd0)
+        relu_bwd(dd0, a["d0"], dd0)
+        self._wgrad("d0", a["u0"], a["e0"], dd0)
+        du0, de0 = like(a["u0"]), like(a["e0"])
+        self._data_grad("d0", dd0, du0, de0)
+        dd1 = up2(du0, backward=True, out=like(a["d1"]))
+        relu_bwd(dd1, a["d1"], dd1)
+        self._wgrad("d1", a["u1"], a["e1"], dd1)
+        du1, de1 = like(a["u1"]), like(a["e1"])
+        self._data_grad("d1", dd1, du1, de1)
+        dd2 = up2(du1, backward=True, out=like(a["d2"]))
+        relu_bwd(dd2, a["d2"], dd2)
+        self._wgrad("d2", a["u2"], a["e2"], dd2)
+        du2, de2 = like(a["u2"]), like(a["e2"])
+        self._data_grad("d2", dd2, du2, de2)
+        db_ = up2(du2, backward=True, out=like(a["b"]))
+        relu_bwd(db_, a["b"], db_)
+        self._wgrad("b", a["p2"], None, db_)
+        dp2 = like(a["p2"])
+        self._data_grad("b", db_, dp2)
+        t = pool2(dp2, backward=True, out=like(a["e2"]))
+        add(de2, t, de2)
+        relu_bwd(de2, a["e2"], de2)
+        self._wgrad("e2", a["p1"], None, de2)
+        dp1 = like(a["p1"])
+        self._data_grad("e2", de2, dp1)
+        t = pool2(dp1, backward=True, out=like(a["e1"]))
+        add(de1, t, de1)
+        relu_bwd(de1, a["e1"], de1)
+        self._wgrad("e1", a["p0"], None, de1)
+        dp0 = like(a["p0"])
+        self._data_grad("e1", de1, dp0)
+        t = pool2(dp0, backward=True, out=like(a["e0"]))
+        add(de0, t, de0)
+        relu_bwd(de0, a["e0"], de0)
+        self._wgrad("e0", a["x0"], None, de0)
+        del self.acts
+
+    def adam(self, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+        self.step_count += 1
+        lib = load()
+        for k in self.p:
+            _check(lib.rt3d_dn_adam(_p(self.p[k]), _p(self.g[k]), _p(self.m1[k]), _p(self.m2[k]), _p(self.pb[k]),
+                                    self.p[k].numel(), lr, b1, b2, eps, self.step_count, _s()), "rt3d_dn_adam")
+            _check(lib.rt3d_dn_adam(_p(self.bias[k]), _p(self.gbias[k]), _p(self.mb1[k]), _p(self.mb2[k]), None,
+                                    self.bias[k].numel(), lr, b1, b2, eps, self.step_count, _s()), "rt3d_dn_adam")
+
+
+# ---------------------------------------------------------------------------
+# Data transform, loss, training step and inference
+# ---------------------------------------------------------------------------
+
+def features(hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, dz: float, scale: float):
+    """BF16 features [D][H][W][16] and FP32 residual base [D][H][W][2]."""
+    D, H, W = hdir.shape
+    feat = bf16_empty(D, H, W, CPAD)
+    base = torch.empty(D, H, W, NOUT, dtype=torch.float32, device=hdir.device)
+    _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), float(dz), float(scale), hdir.numel(), CPAD,
+                                   _p(feat), _p(base), _s()), "rt3d_dn_features")
+    return feat, base
+
+
+def field_scale(hdir: torch.Tensor, hdif: torch.Tensor) -> float:
+    s = float((hdir.double().mean() + hdif.double().mean()).item()) / 2.0
+    return s if s > 0 else 1.0
+
+
+def mse(out: torch.Tensor, base: torch.Tensor, target: Optional[torch.Tensor], want_grad: bool):
+    nvox = base.shape[0] * base.shape[1] * base.shape[2]
+    pred = torch.empty_like(base)
+    dout = bf16_empty(*out.shape) if want_grad else None
+    loss = torch.zeros(1, dtype=torch.float64, device=out.device) if target is not None else None
+    _check(load().rt3d_dn_mse(_p(out), HEAD, _p(base), _p(target), NOUT, nvox, _p(pred), _p(dout), _p(loss), _s()),
+           "rt3d_dn_mse")
+    return pred, dout, (None if loss is None else loss / (nvox * NOUT))
+
+
+def train_step(net: Denoiser, feat, base, target, lr: float) -> torch.Tensor:
+    out = net.forward(feat, keep=True)
+    _, dout, loss = mse(out, base, target, want_grad=True)
+    net.backward(dout)
+    net.adam(lr)
+    return loss
+
+
+def denoise(net: Denoiser, hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, dz: float):
+    """Inference: denoised (hdir, hdif), same units as the inputs."""
+    s = field_scale(hdir, hdif)
+    feat, base = features(hdir, hdif, k_ext, dz, s)
+    out = net.forward(feat)
+    pred, _, _ = mse(out, base, None, want_grad=False)
+    od, of = torch.empty_like(hdir), torch.empty_like(hdif)
+    _check(load().rt3d_dn_unfeature(_p(pred), float(s), hdir.numel(), _p(od), _p(of), _s()), "rt3d_dn_unfeature")
+    return od, of

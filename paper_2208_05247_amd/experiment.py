@@ -1,0 +1,233 @@
+"""Time to a 5 % heating-rate RMS error: plain tracing vs batched tracing +
+the learned denoiser, on one MI355X.
+
+Error measure (after the paper's convergence study, sec. 3.2 and figure 2,
+which compares against a benchmark with 16384 photons per column):
+  eps(N) = sqrt( mean_cells (HR_N - HR_ref)^2 - var_ref ) / sqrt( mean HR_ref^2 - var_ref )
+HR is the total (direct + diffuse) heating rate in K/day of every 3D cell;
+the reference is the mean of two independent halves A and B, and its own
+noise variance var_ref = mean (A - B)^2 / 4 is subtracted.
+
+Plain: eps = a N^-1/2 is fitted over a sweep of photons per column (the
+paper's convergence law), kernel time is fitted linearly in N, and the time
+at eps = 5 % follows.  Denoised: the smallest photons-per-column whose
+denoised field reaches 5 %, timed as batched tracing + network inference.
+
+The denoiser is trained on pairs the tracer generates: random cumulus
+fields on the evaluation grid spacing, random sun and g-point sets, inputs
+at a few photons per column, targets at 1024 per column.
+
+  python -m paper_2208_05247_amd.experiment [--quick] [--out result.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import denoise as dn
+from . import rt3d
+from . import synthetic as syn
+
+F_TOD = 1000.0     # W m^-2, nominal downward flux at the domain top
+CP = 1004.0        # J kg^-1 K^-1
+TARGET_EPS = 0.05
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def layer_scale(grid) -> torch.Tensor:
+    """Normalised absorption -> heating rate (K/day): F 86400 / (rho(z) c_p dz)
+    with rho(z) = 1.2 exp(-z / 8 km) kg m^-3 at the level centres."""
+    z = (np.arange(grid.nz) + 0.5) * grid.dz
+    rho = 1.2 * np.exp(-z / 8000.0)
+    return torch.tensor(F_TOD * 86400.0 / (rho * CP * grid.dz), dtype=torch.float64, device="cuda")
+
+
+def multinomial_counts(weights, total, seed):
+    return np.random.default_rng(seed).multinomial(int(total), weights).astype(np.uint64)
+
+
+class Tracer:
+    """Batched tracing of one scene into heating-rate fields (K/day)."""
+
+    def __init__(self, wl: "syn.BatchedWorkload", brick=(8, 8, 8)):
+        self.wl = wl
+        self.m = wl.medium
+        self.grid = self.m.grid
+        self.dm = rt3d.DeviceBatchedMedium.from_host(self.m)
+        self.brick = brick
+        opt = rt3d.options(brick=brick)
+        self.ws = rt3d.alloc_workspace(rt3d.workspace_size_batched(self.grid, self.m.n_gpoints, opt))
+        self.out = rt3d.alloc_tallies(self.grid)
+        self.ls = layer_scale(self.grid)
+        self.k_ext = None
+
+    def k_ext_mean(self) -> torch.Tensor:
+        """Flux-weighted extinction field (network input)."""
+        if self.k_ext is None:
+            kg = (self.m.weights[:, None] * self.m.k_gas.astype(np.float64)).sum(axis=0)
+            ke = self.m.k_cloud.astype(np.float64) + kg[:, None, None]
+            self.k_ext = torch.from_numpy(ke.astype(np.float32)).cuda()
+        return self.k_ext
+
+    def heating(self, per_col: float, seed: int):
+        total = max(1, int(round(per_col * self.grid.ncol)))
+        counts = multinomial_counts(self.m.weights, total, seed)
+        raw = rt3d.trace_batched(self.dm, self.wl.sza, self.wl.azimuth, counts, seed, brick=self.brick,
+                                 out=self.out, workspace=self.ws, timed=True)
+        kms = rt3d.last_trace_ms()
+        fin = rt3d.finalize(self.grid, raw, total, layer_scale=self.ls)
+        return fin["abs_dir"], fin["abs_dif"], kms, total
+
+
+def eps_against(h: torch.Tensor, ref_a: torch.Tensor, ref_b: torch.Tensor) -> float:
+    ref = 0.5 * (ref_a.double() + ref_b.double())
+    var_ref = float(((ref_a.double() - ref_b.double()) ** 2).mean().item()) / 4.0
+    mse = float(((h.double() - ref) ** 2).mean().item()) - var_ref
+    power = float((ref ** 2).mean().item()) - var_ref
+    return math.sqrt(max(mse, 0.0) / power)
+
+
+def scene(seed: int, nx: int, ny: int, nz: int, dx: float, dz: float, sza=None, az=None, n_gp=112,
+          photons=1 << 20):
+    rng = np.random.default_rng(10_000 + seed)
+    sza = float(rng.uniform(0.0, 65.0)) if sza is None else sza
+    az = float(rng.uniform(0.0, 360.0)) if az is None else az
+    alb = rng.uniform(0.1, 0.3, (ny, nx)).astype(np.float32)
+    wl = syn.batched_cumulus(seed=seed, nx=nx, ny=ny, nz=nz, dx=dx, dz=dz, n_gp=n_gp, photons=photons,
+                             sza=sza, albedo=alb)
+    wl.azimuth = az
+    return wl
+
+
+def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: int, dx: float, dz: float,
+          low=(4, 8, 16, 32), high: int = 1024, lr: float = 1e-3, seed0: int = 0):
+    """Train on tracer-generated pairs; one new field per round."""
+    losses = []
+    t0 = time.perf_counter()
+    step = 0
+    total_steps = n_fields * steps_per_field
+    for f in range(n_fields):
+        wl = scene(seed0 + f, nx, nx, nz, dx, dz)
+        tr = Tracer(wl)
+        tdir, tdif, _, _ = tr.heating(high, seed=7919 * f + 1)
+        kext = tr.k_ext_mean()
+        for s in range(steps_per_field):
+            per_col = low[(f + s) % len(low)]
+            ndir, ndif, _, _ = tr.heating(per_col, seed=7919 * f + 100 + s)
+            sc = dn.field_scale(ndir, ndif)
+            feat, base = dn.features(ndir, ndif, kext, dz, sc)
+            target = torch.stack([tdir / sc, tdif / sc], dim=-1).float().contiguous()
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / total_steps))
+            loss = dn.train_step(net, feat, base, target, lr_t)
+            losses.append(float(loss.item()))
+            step += 1
+        if f % 8 == 0 or f == n_fields - 1:
+            log(f"train field {f + 1}/{n_fields} loss {np.mean(losses[-steps_per_field:]):.4g} "
+                f"({time.perf_counter() - t0:.0f} s)")
+        del tr
+    return losses
+
+
+def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(4, 16, 64, 256, 1024), low=(4, 8, 16, 32, 64, 128)):
+    tr = Tracer(wl)
+    g = tr.grid
+    log("reference halves ...")
+    half = ref_per_col // 2
+    a_dir, a_dif, ka, _ = tr.heating(half, seed=424242)
+    ref_a = (a_dir + a_dif).clone()
+    b_dir, b_dif, kb, _ = tr.heating(half, seed=525252)
+    ref_b = (b_dir + b_dif).clone()
+    log(f"reference kernel ms {ka:.1f} + {kb:.1f}")
+    plain = []
+    for n in sweep:
+        hd, hf, kms, total = tr.heating(n, seed=1000 + n)
+        e = eps_against(hd + hf, ref_a, ref_b)
+        plain.append({"photons_per_column": n, "kernel_ms": kms, "eps": e})
+        log(f"plain N={n}: eps {e:.4f}, kernel {kms:.1f} ms")
+    Ns = np.array([p["photons_per_column"] for p in plain], dtype=np.float64)
+    E = np.array([p["eps"] for p in plain])
+    T = np.array([p["kernel_ms"] for p in plain])
+    # eps = a N^-1/2 (least squares on eps * sqrt(N)), time = t0 + c N
+    a = float(np.exp(np.mean(np.log(E * np.sqrt(Ns)))))
+    c, t0 = np.polyfit(Ns, T, 1)
+    n5 = (a / TARGET_EPS) ** 2
+    t_plain = float(t0 + c * n5)
+    kext = tr.k_ext_mean()
+    den = []
+    reached = None
+    for n in low:
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        hd, hf, kms, total = tr.heating(n, seed=2000 + n)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
+        od, of = dn.denoise(net, hd, hf, kext, g.dz)
+        torch.cuda.synchronize()
+        w2 = time.perf_counter()
+        e_raw = eps_against(hd + hf, ref_a, ref_b)
+        e = eps_against(od + of, ref_a, ref_b)
+        rec = {"photons_per_column": n, "trace_ms": (w1 - w0) * 1e3, "trace_kernel_ms": kms,
+               "inference_ms": (w2 - w1) * 1e3, "eps_raw": e_raw, "eps_denoised": e}
+        den.append(rec)
+        log(f"denoised N={n}: eps raw {e_raw:.4f} -> {e:.4f}; trace {rec['trace_ms']:.1f} ms, "
+            f"inference {rec['inference_ms']:.1f} ms")
+        if e <= TARGET_EPS and reached is None:
+            reached = rec
+            break
+    res = {"plain_fit": {"a": a, "photons_per_column_at_5pct": n5, "t0_ms": float(t0), "ms_per_unit_N": float(c),
+                         "time_to_5pct_ms": t_plain},
+           "plain_sweep": plain, "denoised": den, "reference_photons_per_column": ref_per_col}
+    if reached:
+        t_dn = reached["trace_ms"] + reached["inference_ms"]
+        res["denoised_time_to_5pct_ms"] = t_dn
+        res["speedup"] = t_plain / t_dn
+    else:
+        res["denoised_time_to_5pct_ms"] = None
+        res["speedup"] = None
+    # what the network gains at equal photons: raw vs denoised error
+    res["gain_at_equal_photons"] = [{"photons_per_column": d["photons_per_column"],
+                                     "eps_raw": d["eps_raw"], "eps_denoised": d["eps_denoised"]} for d in den]
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="small grids and few fields (smoke run)")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--train-fields", type=int, default=200)
+    ap.add_argument("--steps-per-field", type=int, default=4)
+    args = ap.parse_args()
+    torch.manual_seed(0)
+    if args.quick:
+        tr_nx, ev_nx, nz, dx, dz, nf, ref = 64, 128, 64, 25.0, 20.0, 6, 4096
+    else:
+        tr_nx, ev_nx, nz, dx, dz, nf, ref = 256, 1024, 128, 25.0, 20.0, args.train_fields, 16384
+    net = dn.Denoiser(base=32, seed=0)
+    log(f"denoiser parameters: {net.n_params()}")
+    t0 = time.perf_counter()
+    losses = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz)
+    train_s = time.perf_counter() - t0
+    wl = scene(99_999, ev_nx, ev_nx, nz, dx, dz, sza=60.0, az=0.0, photons=1 << 30)
+    res = evaluate(net, wl, ref)
+    res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,
+                "final_train_loss": float(np.mean(losses[-20:])),
+                "eval_grid": [ev_nx, ev_nx, nz], "cell_m": [dx, dx, dz], "sza": 60.0, "g_points": 112,
+                "train_grid": [tr_nx, tr_nx, nz]})
+    log(json.dumps(res))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

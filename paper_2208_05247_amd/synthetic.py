@@ -298,8 +298,8 @@ def batched_cumulus(seed: int = 1, nx: int = 512, ny: int = 512, nz: int = 96, d
     weights) so every photon carries the same energy."""
     grid = Grid(nx, ny, nz, dx, dx, dz)
     rng = np.random.default_rng(seed)
-    if n_blobs is None:
-        n_blobs = int(round(200 * (nx * ny) / (256 * 256)))
+    if n_blobs is None:  # the LES case's density: 200 blobs per 12.8 x 12.8 km
+        n_blobs = max(1, int(round(200 * (nx * dx) * (ny * dx) / 12800.0 ** 2)))
     amp = lambda r: float(0.02 * np.exp(0.5 * r.standard_normal()))
     kc = cloud_blobs(grid, rng, n_blobs, amp, z_range=(700.0, 2500.0), layer=(700.0, 2500.0),
                      centre_margin=True).astype(np.float32)

@@ -1,0 +1,154 @@
+"""BF16 MFMA denoiser kernels against the FP64 CPU reference.
+
+Convolution forward, data gradient (flipped kernel) and weight gradient are
+compared on BF16-representable inputs, where the only differences are FP32
+accumulation order (tight tolerance); the whole network (forward, every
+gradient) is compared with a tolerance that allows for BF16 storage of the
+activations between layers."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import torch.nn.functional as F  # noqa: E402
+
+from oracle import denoise_ref as dr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dn():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_2208_05247_amd import denoise
+    denoise.load()
+    return denoise
+
+
+def bf(x):
+    """Round a float tensor to BF16 and back (CPU float64)."""
+    return x.to(torch.bfloat16).double()
+
+
+def rel(a, b):
+    return float((a - b).norm() / max(b.norm(), 1e-30))
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 37, 16, 32, 64, 3), (4, 4, 64, 32, 0, 32, 3), (2, 3, 20, 32, 0, 32, 1)])
+def test_conv_forward_and_gradients(dn, shape):
+    D, H, W, c1, c2, cout, k = shape
+    g = torch.Generator().manual_seed(7)
+    cin = c1 + c2
+    x = bf(torch.randn(D, H, W, cin, generator=g, dtype=torch.float64))
+    w = bf(torch.randn(cout, k ** 3, cin, generator=g, dtype=torch.float64) * 0.2)
+    b = torch.randn(cout, generator=g, dtype=torch.float64) * 0.1
+    dev = lambda t, dt=torch.bfloat16: t.to(dt).cuda().contiguous()
+    x1 = dev(x[..., :c1])
+    x2 = dev(x[..., c1:]) if c2 else None
+    yf = torch.empty(D, H, W, cout, dtype=torch.float32, device="cuda")
+    y = torch.empty(D, H, W, cout, dtype=torch.bfloat16, device="cuda")
+    dn.conv_fwd(x1, x2, dev(w), dev(b, torch.float32), True, cout, k, y1=y, yf=yf)
+    xt = x.permute(3, 0, 1, 2).unsqueeze(0)
+    ref = torch.relu(dr.conv(xt, w, b.float().double(), k))[0].permute(1, 2, 3, 0)
+    assert rel(yf.double().cpu(), ref) < 1e-5
+    assert torch.allclose(y.double().cpu(), bf(yf.double().cpu()))
+    # data gradient = conv of dz with the flipped kernel; weight gradient
+    dz = bf(torch.randn(D, H, W, cout, generator=g, dtype=torch.float64))
+    xr = xt.clone().requires_grad_(True)
+    wr = w.clone().requires_grad_(True)
+    out = dr.conv(xr, wr, None, k)
+    out.backward(dz.permute(3, 0, 1, 2).unsqueeze(0))
+    gx = xr.grad[0].permute(1, 2, 3, 0)
+    wt = torch.empty(cin, k ** 3, cout, dtype=torch.bfloat16, device="cuda")
+    dn.flip(dev(w), cout, cin, k, wt)
+    if cin % 32 == 0:
+        dxf = torch.empty(D, H, W, cin, dtype=torch.float32, device="cuda")
+        dn.conv_fwd(dev(dz), None, wt, None, False, cin, k, yf=dxf)
+        assert rel(dxf.double().cpu(), gx) < 1e-5
+    dw = torch.zeros(cout, k ** 3, cin, dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    dn.conv_wgrad(x1, x2, dev(dz), cout, k, dw, db)
+    assert rel(dw.double().cpu(), wr.grad) < 1e-5
+    assert rel(db.double().cpu(), dz.sum(dim=(0, 1, 2))) < 1e-5
+
+
+def test_pool_and_upsample(dn):
+    g = torch.Generator().manual_seed(3)
+    x = bf(torch.randn(4, 6, 8, 16, generator=g, dtype=torch.float64))
+    xd = x.to(torch.bfloat16).cuda()
+    p = dn.pool2(xd).double().cpu()
+    ref = F.avg_pool3d(x.permute(3, 0, 1, 2).unsqueeze(0), 2)[0].permute(1, 2, 3, 0)
+    assert torch.allclose(p, bf(ref), atol=1e-2, rtol=1e-2)
+    u = dn.up2(xd).double().cpu()
+    assert torch.equal(u, dr.up(x.permute(3, 0, 1, 2).unsqueeze(0))[0].permute(1, 2, 3, 0))
+    gu = dn.up2(dn.up2(xd), backward=True, out=torch.empty_like(xd)).double().cpu()
+    assert torch.allclose(gu, bf(8 * x), rtol=1e-2)
+    gp = dn.pool2(dn.pool2(xd), backward=True, out=torch.empty_like(xd)).double().cpu()
+    assert torch.allclose(gp, bf(dr.up(ref.permute(3, 0, 1, 2).unsqueeze(0))[0].permute(1, 2, 3, 0) / 8),
+                          atol=1e-2, rtol=2e-2)
+
+
+def test_network_gradients_match_fp64_reference(dn):
+    """One forward + backward of the full 4-level network (32 base channels)
+    on a 16x16x16 field: loss, prediction and every weight / bias gradient
+    against the FP64 autograd reference run with the same BF16 weights and
+    inputs."""
+    torch.manual_seed(0)
+    net = dn.Denoiser(base=32, seed=3)
+    # give the head real weights so every layer receives gradient
+    g = torch.Generator().manual_seed(5)
+    net.p["head"].copy_((torch.randn(net.p["head"].shape, generator=g) * 0.1).cuda())
+    net.p["head"][2:] = 0
+    net.pb["head"].copy_(net.p["head"].to(torch.bfloat16))
+    for k in net.bias:
+        net.bias[k].copy_((torch.randn(net.bias[k].shape, generator=g) * 0.05).cuda())
+    D = H = W = 16
+    hdir = torch.rand(D, H, W, generator=g).cuda() * 2
+    hdif = torch.rand(D, H, W, generator=g).cuda()
+    kext = torch.rand(D, H, W, generator=g).cuda() * 0.05
+    feat, base = dn.features(hdir, hdif, kext, 20.0, 1.0)
+    target = (base + 0.3 * torch.randn(base.shape, generator=g).cuda()).contiguous()
+    out = net.forward(feat, keep=True)
+    pred, dout, loss = dn.mse(out, base, target, want_grad=True)
+    net.backward(dout)
+    params = {k: net.pb[k].double().cpu() for k in net.p}
+    params["e0"] = params["e0"][:, :, :16]
+    biases = {k: net.bias[k].double().cpu() for k in net.bias}
+    rloss, gw, gb, rpred = dr.loss_and_grads(params, biases, feat.double().cpu(), base.double().cpu(),
+                                             target.double().cpu())
+    say("loss gpu", loss.item(), "ref", rloss)
+    assert abs(loss.item() - rloss) <= 2e-2 * rloss
+    assert rel(pred.double().cpu(), rpred) < 2e-2
+    for k in dr.ORDER:
+        e = rel(net.g[k].double().cpu(), gw[k])
+        cos = float((net.g[k].double().cpu() * gw[k]).sum() / (net.g[k].double().cpu().norm() * gw[k].norm()))
+        say("grad", k, "rel err", round(e, 5), "cos", round(cos, 6))
+        assert e < 6e-2 and cos > 0.998, k
+        eb = rel(net.gbias[k].double().cpu(), gb[k])
+        assert eb < 6e-2, (k, "bias", eb)
+
+
+def test_training_reduces_loss(dn):
+    """A few Adam steps on one denoising pair lower the loss."""
+    g = torch.Generator().manual_seed(11)
+    D = H = W = 32
+    clean = torch.rand(D, H, W, generator=g) ** 4
+    noisy_dir = (clean * (1 + 0.5 * torch.randn(D, H, W, generator=g))).clamp_min(0).cuda()
+    noisy_dif = (clean * (1 + 0.5 * torch.randn(D, H, W, generator=g))).clamp_min(0).cuda()
+    kext = clean.cuda() * 0.02
+    net = dn.Denoiser(base=32, seed=1)
+    s = dn.field_scale(noisy_dir, noisy_dif)
+    feat, base = dn.features(noisy_dir, noisy_dif, kext, 20.0, s)
+    target = torch.stack([clean / s, clean / s], dim=-1).float().cuda().contiguous()
+    losses = [dn.train_step(net, feat, base, target, 1e-3).item() for _ in range(30)]
+    say("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.7 * losses[0]
+    d1, d2 = dn.denoise(net, noisy_dir, noisy_dif, kext, 20.0)
+    assert d1.shape == noisy_dir.shape and torch.isfinite(d1).all() and (d1 >= 0).all()

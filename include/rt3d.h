@@ -89,8 +89,8 @@ extern "C" {
 typedef enum {
     RT3D_OK = 0,
     RT3D_EINVAL = 1,  /* bad argument: null pointer, non-positive size, brick
-                         not dividing the grid, sza outside [0,90), photons 0,
-                         workspace too small, too many cells */
+                         not dividing the grid, sza outside [0,90), photons 0
+                         or >= 2^33, workspace too small, too many cells */
     RT3D_EDOMAIN = 2, /* RT3D_FLAG_VALIDATE found a field value out of range */
     RT3D_EDEVICE = 3  /* a HIP runtime call failed; see rt3d_last_device_error */
 } rt3d_status;
@@ -248,6 +248,8 @@ rt3d_status rt3d_majorant_build(const rt3d_grid* grid, const float* k_ext,
                                 float* majorant, void* stream);
 
 /* Trace `photons` photon packets (sec. 2.3) entering the top of the domain
+ * (1 <= photons < 2^33 per call, so that photons * 2^31 fits the uint64
+ * ledger; larger runs are several calls with ACCUMULATE)
  * with the sun at (sza_deg, azimuth_deg) and write raw tallies to `out`
  * (zeroed first unless RT3D_FLAG_ACCUMULATE).  surface_albedo: device FP32
  * [ny][nx] in [0,1].  seed: Philox key.  opt: host pointer or NULL for
@@ -268,7 +270,7 @@ size_t rt3d_workspace_size_batched(const rt3d_grid* grid, int32_t n_gpoints, con
 /* Trace n_gpoints g-points (1 <= n_gpoints <= RT3D_MAX_GPOINTS) of the
  * factored medium in ONE persistent launch and write broadband raw tallies
  * (the sum over g-points) to `out`.  photons: HOST array [n_gpoints] of photon
- * counts (zeros allowed, total > 0); g-point n is traced exactly as
+ * counts (zeros allowed, 0 < total < 2^33); g-point n is traced exactly as
  * rt3d_trace would trace its fields with photons[n] photons and Philox key
  * seed + n, so with photon counts proportional to the g-points' shares of
  * the TOD flux every photon carries the same energy and the broadband tally

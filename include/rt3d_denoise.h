@@ -99,11 +99,12 @@ rt3d_status rt3d_dn_adam(float* p, const float* g, float* m1, float* m2, uint16_
 rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* stream);
 
 /* Network input per voxel: channel 0 = hdir/scale, 1 = hdif/scale,
- * 2 = ln(1 + 20 k_ext dz), channels 3..cpad-1 = 0 (feat BF16 [vox][cpad]);
- * base FP32 [vox][2] = (hdir/scale, hdif/scale), the residual the network
- * corrects.  hdir, hdif: FP32 heating fields; k_ext FP32 [vox]. */
-rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, float dz, float scale,
-                             uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream);
+ * 2 = ln(1 + 20 k_ext dz), 3 = ln(1 + 200 k_abs dz), channels 4..cpad-1 = 0
+ * (feat BF16 [vox][cpad]); base FP32 [vox][2] = (hdir/scale, hdif/scale), the
+ * residual the network corrects.  hdir, hdif: FP32 heating fields; k_ext,
+ * k_abs: FP32 [vox] extinction and absorption coefficients (m^-1). */
+rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
+                             float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream);
 
 /* hdir[v] = max(pred[v][0], 0) scale, hdif[v] = max(pred[v][1], 0) scale. */
 rt3d_status rt3d_dn_unfeature(const float* pred, float scale, uint64_t nvox, float* hdir, float* hdif,

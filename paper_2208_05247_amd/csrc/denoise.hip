@@ -357,19 +357,21 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict
 }
 
 // Input features per voxel: scaled direct and diffuse heating, log optical
-// thickness of the cell, zero padding to cpad channels (BF16); the scaled
-// heating is also written as the FP32 residual base [v][2].
+// thickness for extinction and for absorption of the cell, zero padding to
+// cpad channels (BF16); the scaled heating is also written as the FP32
+// residual base [v][2].
 __global__ void features_kernel(const float* __restrict__ hdir, const float* __restrict__ hdif,
-                                const float* __restrict__ k_ext, float dz, float inv_scale, size_t nvox, int cpad,
-                                uint16_t* __restrict__ feat, float* __restrict__ base) {
+                                const float* __restrict__ k_ext, const float* __restrict__ k_abs, float dz,
+                                float inv_scale, size_t nvox, int cpad, uint16_t* __restrict__ feat,
+                                float* __restrict__ base) {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
         const float a = hdir[v] * inv_scale, b = hdif[v] * inv_scale;
-        const float c = __logf(1.0f + 20.0f * k_ext[v] * dz);
         uint16_t* f = feat + v * cpad;
         f[0] = f2bf(a);
         f[1] = f2bf(b);
-        f[2] = f2bf(c);
-        for (int q = 3; q < cpad; ++q) f[q] = 0;
+        f[2] = f2bf(__logf(1.0f + 20.0f * k_ext[v] * dz));
+        f[3] = f2bf(__logf(1.0f + 200.0f * k_abs[v] * dz));
+        for (int q = 4; q < cpad; ++q) f[q] = 0;
         base[2 * v] = a;
         base[2 * v + 1] = b;
     }
@@ -523,11 +525,12 @@ rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* strea
     return RT3D_OK;
 }
 
-rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, float dz, float scale,
-                             uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream) {
-    if (!hdir || !hdif || !k_ext || !feat || !base || cpad < 16 || cpad % 16 || !(scale > 0.0f)) return RT3D_EINVAL;
+rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
+                             float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream) {
+    if (!hdir || !hdif || !k_ext || !k_abs || !feat || !base || cpad < 16 || cpad % 16 || !(scale > 0.0f))
+        return RT3D_EINVAL;
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, hdir, hdif, k_ext,
-                       dz, 1.0f / scale, (size_t)nvox, cpad, feat, base);
+                       k_abs, dz, 1.0f / scale, (size_t)nvox, cpad, feat, base);
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }

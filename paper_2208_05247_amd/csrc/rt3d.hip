@@ -284,8 +284,9 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             if (avail < need) {
                 if ((int)__lane_id() == leader) base = atomicAdd(P.queue, (unsigned long long)P.pool);
                 base = __shfl(base, leader);
-                base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
-                       __builtin_amdgcn_readfirstlane((uint32_t)base);
+                // readfirstlane returns a signed int: widen through uint32_t
+                base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
             }
             if (!alive) {
                 const uint32_t rank = (uint32_t)__popcll(dead & lane_mask_lt());
@@ -877,7 +878,8 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
         if (total + photons[n] < total) return RT3D_EINVAL;
         total += photons[n];
     }
-    if (total == 0) return RT3D_EINVAL;
+    // the ledger holds photons * 2^31 in uint64
+    if (total == 0 || total >= (1ull << 33)) return RT3D_EINVAL;
     if (o.photon_offset + total < o.photon_offset) return RT3D_EINVAL;
     const Layout lay = layout_of(s, ngp, factored);
     if (!workspace || workspace_bytes < lay.total || ((uintptr_t)workspace & 255)) return RT3D_EINVAL;

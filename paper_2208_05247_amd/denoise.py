@@ -4,7 +4,7 @@ encoder-decoder built from its kernels.
 Network (4 resolution levels, 32 base channels, BF16 weights and
 activations, FP32 accumulation on the matrix cores):
 
-  x0 [16: hdir/s, hdif/s, ln(1+20 k_ext dz), 0...]
+  x0 [16: hdir/s, hdif/s, ln(1+20 k_ext dz), ln(1+200 k_abs dz), 0...]
   e0 = relu(conv3 x0 -> 32)           level 0
   e1 = relu(conv3 pool(e0) -> 64)     level 1
   e2 = relu(conv3 pool(e1) -> 128)    level 2
@@ -30,7 +30,7 @@ import torch
 
 from . import rt3d
 
-CPAD = 16          # input feature channels (3 used)
+CPAD = 16          # input feature channels (4 used)
 HEAD = 32          # head output channels (2 used)
 NOUT = 2
 LEVELS = 4
@@ -62,7 +62,7 @@ def load():
         "rt3d_dn_mse": [P, I, P, P, I, U, P, P, P, P],
         "rt3d_dn_adam": [P, P, P, P, P, U, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, I, P],
         "rt3d_dn_to_bf16": [P, P, U, P],
-        "rt3d_dn_features": [P, P, P, ctypes.c_float, ctypes.c_float, U, I, P, P, P],
+        "rt3d_dn_features": [P, P, P, P, ctypes.c_float, ctypes.c_float, U, I, P, P, P],
         "rt3d_dn_unfeature": [P, ctypes.c_float, U, P, P, P],
     }
     for name, args in sig.items():
@@ -189,7 +189,7 @@ class Denoiser:
             std = math.sqrt(2.0 / fan_in) if L.name != "head" else 1e-3
             w = torch.randn(L.cout, taps, L.c1 + L.c2, generator=g, dtype=torch.float32) * std
             if L.name == "e0":
-                w[:, :, 3:] = 0.0  # padding channels carry nothing
+                w[:, :, 4:] = 0.0  # padding channels carry nothing
             if L.name == "head":
                 w[NOUT:] = 0.0
             self.p[L.name] = w.to(device).contiguous()
@@ -322,13 +322,14 @@ class Denoiser:
 # Data transform, loss, training step and inference
 # ---------------------------------------------------------------------------
 
-def features(hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, dz: float, scale: float):
+def features(hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, k_abs: torch.Tensor, dz: float,
+             scale: float):
     """BF16 features [D][H][W][16] and FP32 residual base [D][H][W][2]."""
     D, H, W = hdir.shape
     feat = bf16_empty(D, H, W, CPAD)
     base = torch.empty(D, H, W, NOUT, dtype=torch.float32, device=hdir.device)
-    _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), float(dz), float(scale), hdir.numel(), CPAD,
-                                   _p(feat), _p(base), _s()), "rt3d_dn_features")
+    _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), _p(k_abs), float(dz), float(scale), hdir.numel(),
+                                   CPAD, _p(feat), _p(base), _s()), "rt3d_dn_features")
     return feat, base
 
 
@@ -355,10 +356,11 @@ def train_step(net: Denoiser, feat, base, target, lr: float) -> torch.Tensor:
     return loss
 
 
-def denoise(net: Denoiser, hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, dz: float):
+def denoise(net: Denoiser, hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, k_abs: torch.Tensor,
+            dz: float):
     """Inference: denoised (hdir, hdif), same units as the inputs."""
     s = field_scale(hdir, hdif)
-    feat, base = features(hdir, hdif, k_ext, dz, s)
+    feat, base = features(hdir, hdif, k_ext, k_abs, dz, s)
     out = net.forward(feat)
     pred, _, _ = mse(out, base, None, want_grad=False)
     od, of = torch.empty_like(hdir), torch.empty_like(hdif)

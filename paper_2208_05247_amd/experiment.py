@@ -14,8 +14,8 @@ at eps = 5 % follows.  Denoised: the smallest photons-per-column whose
 denoised field reaches 5 %, timed as batched tracing + network inference.
 
 The denoiser is trained on pairs the tracer generates: random cumulus
-fields on the evaluation grid spacing, random sun and g-point sets, inputs
-at a few photons per column, targets at 1024 per column.
+fields on the evaluation grid spacing, random sun, surface albedo and
+g-point sets, inputs at 64-1024 photons per column, targets at 8192.
 
   python -m paper_2208_05247_amd.experiment [--quick] [--out result.json]
 """
@@ -71,20 +71,34 @@ class Tracer:
         self.ls = layer_scale(self.grid)
         self.k_ext = None
 
-    def k_ext_mean(self) -> torch.Tensor:
-        """Flux-weighted extinction field (network input)."""
+    def k_mean(self):
+        """Flux-weighted extinction and absorption fields (network inputs)."""
         if self.k_ext is None:
-            kg = (self.m.weights[:, None] * self.m.k_gas.astype(np.float64)).sum(axis=0)
-            ke = self.m.k_cloud.astype(np.float64) + kg[:, None, None]
+            w = self.m.weights[:, None]
+            kg = (w * self.m.k_gas.astype(np.float64)).sum(axis=0)
+            kga = (w * self.m.k_gas.astype(np.float64) * (1.0 - self.m.ssa_gas.astype(np.float64))).sum(axis=0)
+            kc = self.m.k_cloud.astype(np.float64)
+            ke = kc + kg[:, None, None]
+            ka = kc * (1.0 - self.m.ssa_cloud.astype(np.float64)) + kga[:, None, None]
             self.k_ext = torch.from_numpy(ke.astype(np.float32)).cuda()
-        return self.k_ext
+            self.k_abs = torch.from_numpy(ka.astype(np.float32)).cuda()
+        return self.k_ext, self.k_abs
 
-    def heating(self, per_col: float, seed: int):
+    def heating(self, per_col: float, seed: int, chunk: int = 1 << 31):
+        """Heating fields of `per_col` photons per column; runs of more than
+        `chunk` photons are traced as several launches with independent
+        seeds (seed + 1000 k) accumulated into the same tallies."""
         total = max(1, int(round(per_col * self.grid.ncol)))
-        counts = multinomial_counts(self.m.weights, total, seed)
-        raw = rt3d.trace_batched(self.dm, self.wl.sza, self.wl.azimuth, counts, seed, brick=self.brick,
-                                 out=self.out, workspace=self.ws, timed=True)
-        kms = rt3d.last_trace_ms()
+        nchunk = -(-total // chunk)
+        kms = 0.0
+        raw = None
+        for k in range(nchunk):
+            part = total // nchunk + (1 if k < total % nchunk else 0)
+            counts = multinomial_counts(self.m.weights, part, seed + 1000 * k)
+            raw = rt3d.trace_batched(self.dm, self.wl.sza, self.wl.azimuth, counts, seed + 1000 * k,
+                                     brick=self.brick, out=self.out, workspace=self.ws, timed=True,
+                                     accumulate=k > 0)
+            kms += rt3d.last_trace_ms()
         fin = rt3d.finalize(self.grid, raw, total, layer_scale=self.ls)
         return fin["abs_dir"], fin["abs_dif"], kms, total
 
@@ -110,47 +124,52 @@ def scene(seed: int, nx: int, ny: int, nz: int, dx: float, dz: float, sza=None, 
 
 
 def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: int, dx: float, dz: float,
-          low=(4, 8, 16, 32), high: int = 1024, lr: float = 1e-3, seed0: int = 0):
-    """Train on tracer-generated pairs; one new field per round."""
+          low=(64, 128, 256, 512, 1024), high: int = 8192, lr: float = 1e-3, seed0: int = 0):
+    """Train on tracer-generated pairs: one new random scene per field,
+    `steps_per_field` noisy realisations against one high-photon target."""
     losses = []
     t0 = time.perf_counter()
+    t_steps = 0.0
     step = 0
     total_steps = n_fields * steps_per_field
     for f in range(n_fields):
         wl = scene(seed0 + f, nx, nx, nz, dx, dz)
         tr = Tracer(wl)
-        tdir, tdif, _, _ = tr.heating(high, seed=7919 * f + 1)
-        kext = tr.k_ext_mean()
+        tdir, tdif, _, _ = tr.heating(high, seed=10_000_000 * (f + 1))
+        kext, kabs = tr.k_mean()
         for s in range(steps_per_field):
-            per_col = low[(f + s) % len(low)]
-            ndir, ndif, _, _ = tr.heating(per_col, seed=7919 * f + 100 + s)
+            per_col = low[(f * steps_per_field + s) % len(low)]
+            ndir, ndif, _, _ = tr.heating(per_col, seed=10_000_000 * (f + 1) + 100_000 * (s + 1))
             sc = dn.field_scale(ndir, ndif)
-            feat, base = dn.features(ndir, ndif, kext, dz, sc)
+            feat, base = dn.features(ndir, ndif, kext, kabs, dz, sc)
             target = torch.stack([tdir / sc, tdif / sc], dim=-1).float().contiguous()
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / total_steps))
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
             loss = dn.train_step(net, feat, base, target, lr_t)
             losses.append(float(loss.item()))
+            t_steps += time.perf_counter() - ts
             step += 1
         if f % 8 == 0 or f == n_fields - 1:
             log(f"train field {f + 1}/{n_fields} loss {np.mean(losses[-steps_per_field:]):.4g} "
-                f"({time.perf_counter() - t0:.0f} s)")
+                f"({time.perf_counter() - t0:.0f} s, {1e3 * t_steps / step:.1f} ms per training step)")
         del tr
-    return losses
+    return losses, t_steps / max(step, 1)
 
 
-def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(4, 16, 64, 256, 1024), low=(4, 8, 16, 32, 64, 128)):
+def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024), low=(64, 128, 256, 512, 1024)):
     tr = Tracer(wl)
     g = tr.grid
     log("reference halves ...")
     half = ref_per_col // 2
-    a_dir, a_dif, ka, _ = tr.heating(half, seed=424242)
+    a_dir, a_dif, ka, _ = tr.heating(half, seed=424_000_000)
     ref_a = (a_dir + a_dif).clone()
-    b_dir, b_dif, kb, _ = tr.heating(half, seed=525252)
+    b_dir, b_dif, kb, _ = tr.heating(half, seed=525_000_000)
     ref_b = (b_dir + b_dif).clone()
     log(f"reference kernel ms {ka:.1f} + {kb:.1f}")
     plain = []
     for n in sweep:
-        hd, hf, kms, total = tr.heating(n, seed=1000 + n)
+        hd, hf, kms, total = tr.heating(n, seed=1_000_000 * (1 + n))
         e = eps_against(hd + hf, ref_a, ref_b)
         plain.append({"photons_per_column": n, "kernel_ms": kms, "eps": e})
         log(f"plain N={n}: eps {e:.4f}, kernel {kms:.1f} ms")
@@ -162,16 +181,16 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(4, 16, 64, 256, 1024
     c, t0 = np.polyfit(Ns, T, 1)
     n5 = (a / TARGET_EPS) ** 2
     t_plain = float(t0 + c * n5)
-    kext = tr.k_ext_mean()
+    kext, kabs = tr.k_mean()
     den = []
     reached = None
     for n in low:
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        hd, hf, kms, total = tr.heating(n, seed=2000 + n)
+        hd, hf, kms, total = tr.heating(n, seed=7_000_000_000 + 1_000_000 * n)
         torch.cuda.synchronize()
         w1 = time.perf_counter()
-        od, of = dn.denoise(net, hd, hf, kext, g.dz)
+        od, of = dn.denoise(net, hd, hf, kext, kabs, g.dz)
         torch.cuda.synchronize()
         w2 = time.perf_counter()
         e_raw = eps_against(hd + hf, ref_a, ref_b)
@@ -205,21 +224,23 @@ def main():
     ap.add_argument("--quick", action="store_true", help="small grids and few fields (smoke run)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--train-fields", type=int, default=200)
-    ap.add_argument("--steps-per-field", type=int, default=4)
+    ap.add_argument("--steps-per-field", type=int, default=8)
     args = ap.parse_args()
     torch.manual_seed(0)
     if args.quick:
         tr_nx, ev_nx, nz, dx, dz, nf, ref = 64, 128, 64, 25.0, 20.0, 6, 4096
     else:
-        tr_nx, ev_nx, nz, dx, dz, nf, ref = 256, 1024, 128, 25.0, 20.0, args.train_fields, 16384
+        tr_nx, ev_nx, nz, dx, dz, nf, ref = 128, 1024, 128, 25.0, 20.0, args.train_fields, 16384
     net = dn.Denoiser(base=32, seed=0)
     log(f"denoiser parameters: {net.n_params()}")
     t0 = time.perf_counter()
-    losses = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz)
+    losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz,
+                           high=2048 if args.quick else 8192)
     train_s = time.perf_counter() - t0
     wl = scene(99_999, ev_nx, ev_nx, nz, dx, dz, sza=60.0, az=0.0, photons=1 << 30)
     res = evaluate(net, wl, ref)
     res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,
+                "ms_per_train_step": 1e3 * step_s,
                 "final_train_loss": float(np.mean(losses[-20:])),
                 "eval_grid": [ev_nx, ev_nx, nz], "cell_m": [dx, dx, dz], "sza": 60.0, "g_points": 112,
                 "train_grid": [tr_nx, tr_nx, nz]})

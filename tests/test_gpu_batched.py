@@ -189,3 +189,20 @@ def test_autotuner_picks_valid_options(rt3d, tmp_path):
     ref = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 16, 3, brick=res.options["brick"]))
     got = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 16, 3, **res.options))
     assert np.array_equal(ref["abs_dir"], got["abs_dir"])
+
+
+def test_more_than_2_31_photons_in_one_launch(rt3d):
+    """Photon-id pools past 2^31 (regression: the wave-uniform pool base must
+    be widened without sign extension).  Vacuum over a black surface: every
+    photon ends at the surface after one event."""
+    grid = syn.Grid(4, 4, 1, 10.0, 10.0, 10.0)
+    f = syn.uniform_fields(grid, 0.0, albedo=0.0)
+    df = rt3d.DeviceFields.from_host(f)
+    n = (1 << 31) + 12345
+    h = rt3d.to_host(rt3d.trace(df, 0.0, 0.0, n, 17, brick=(4, 4, 1)))
+    ledger_ok(h, n)
+    assert int(h["sfc_dir"].sum()) == n * W1
+    counts = h["sfc_dir"] // W1
+    assert counts.max() - counts.min() <= 1
+    with pytest.raises(rt3d.Rt3dError):
+        rt3d.trace(df, 0.0, 0.0, 1 << 33, 17, brick=(4, 4, 1))

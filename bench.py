@@ -162,6 +162,7 @@ def main():
     ap.add_argument("--photons", type=int, default=1 << 26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lds-majorant", type=int, default=0)
+    ap.add_argument("--no-merge", action="store_true", help="one tally atomic per deposit")
     ap.add_argument("--brick", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched g-point measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -194,7 +195,7 @@ def main():
 
     def step(seed):
         raw = rt3d.trace(df, wl.sza, wl.azimuth, wl.photons, seed, brick=wl.brick, out=out, workspace=ws,
-                         timed=True, lds_majorant=args.lds_majorant)
+                         timed=True, lds_majorant=args.lds_majorant, merge=not args.no_merge)
         kms = rt3d.last_trace_ms()
         fin = rt3d.finalize(grid, raw, wl.photons)
         return kms, raw["stats"].clone(), fin
@@ -220,7 +221,7 @@ def main():
     mean_kms = sum(kernel_ms) / len(kernel_ms)
     bytes_per_launch = algorithmic_bytes(tot) / args.steps
     achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
-    traffic = measured_traffic(wl.brick, wl.photons) if args.lds_majorant == 0 else None
+    traffic = measured_traffic(wl.brick, wl.photons) if args.lds_majorant == 0 and not args.no_merge else None
     res = {
         "metric": METRIC,
         "value": events / wall,

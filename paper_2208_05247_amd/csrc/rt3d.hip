@@ -533,21 +533,38 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
 // Heating entries of the energy ledger: ledger[ATM_DIR] = sum(abs_dir),
 // ledger[ATM_DIF] = sum(abs_dif), exact uint64 sums (the other entries are
 // counted by the tracing kernel, so the identity still checks that no
-// deposit was lost).  One workgroup per array.
+// deposit was lost).  The two entries are cleared first (clear_atm_kernel);
+// every workgroup adds its partial sums.
+__global__ void clear_atm_kernel(unsigned long long* __restrict__ ledger) {
+    if (threadIdx.x == 0) {
+        ledger[L_ATM_DIR] = 0;
+        ledger[L_ATM_DIF] = 0;
+    }
+}
+
 __global__ void ledger_atm_kernel(const unsigned long long* __restrict__ abs_dir,
                                   const unsigned long long* __restrict__ abs_dif, size_t n,
                                   unsigned long long* __restrict__ ledger) {
-    __shared__ unsigned long long part[1024];
-    const unsigned long long* src = blockIdx.x == 0 ? abs_dir : abs_dif;
-    unsigned long long acc = 0;
-    for (size_t i = threadIdx.x; i < n; i += blockDim.x) acc += src[i];
-    part[threadIdx.x] = acc;
+    __shared__ unsigned long long part[2][256];
+    unsigned long long sd = 0, sf = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        sd += abs_dir[i];
+        sf += abs_dif[i];
+    }
+    part[0][threadIdx.x] = sd;
+    part[1][threadIdx.x] = sf;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            part[0][threadIdx.x] += part[0][threadIdx.x + h];
+            part[1][threadIdx.x] += part[1][threadIdx.x + h];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) ledger[blockIdx.x == 0 ? L_ATM_DIR : L_ATM_DIF] = part[0];
+    if (threadIdx.x == 0) {
+        if (part[0][0]) atomicAdd(&ledger[L_ATM_DIR], part[0][0]);
+        if (part[1][0]) atomicAdd(&ledger[L_ATM_DIF], part[1][0]);
+    }
 }
 
 // Interleave the four SoA property arrays into one 16-byte record per cell,
@@ -1008,8 +1025,10 @@ rt3d_status launch_trace(Launch& L, bool factored, hipStream_t st) {
         HIP_TRY(hipEventRecord(g_t1, st));
         g_timed = true;
     }
-    hipLaunchKernelGGL(ledger_atm_kernel, dim3(2), dim3(1024), 0, st, L.P.abs_dir, L.P.abs_dif, L.s.ncell,
-                       L.P.ledger);
+    hipLaunchKernelGGL(clear_atm_kernel, dim3(1), dim3(64), 0, st, L.P.ledger);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(ledger_atm_kernel, dim3(grid_for(L.s.ncell, 256, 2048)), dim3(256), 0, st, L.P.abs_dir,
+                       L.P.abs_dif, L.s.ncell, L.P.ledger);
     HIP_TRY(hipGetLastError());
     return RT3D_OK;
 }

@@ -19,6 +19,19 @@ Parity status of each function (what pins it, see ``tests/``):
                                   grids, exact ledger, invariances
   direct_transmittance            closed form for horizontally uniform layers
   finalize                        exact rational scaling, checked by hand
+  sobol_points                    radical inverse by digit division; Pascal
+                                  matrix mod 2 (Lucas); (0, m, 2)-net property
+  owen_scramble / sobol_entry     nestedness, uniformity over seeds, nets kept,
+                                  N^-1 convergence on smooth integrals and on
+                                  slanted-sun surface irradiance; the traced
+                                  entry points predicted photon by photon;
+                                  the scramble-seed counter is pinned only by
+                                  bit-equality with the GPU generator
+  two_stream (module)             exact matrix-exponential propagation of the
+                                  same equations, split-layer invariance, pure
+                                  absorber and conservation closed forms,
+                                  thin-layer backscatter by quadrature, exact
+                                  Monte Carlo transport within 6 %
 """
 from __future__ import annotations
 
@@ -35,6 +48,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 W_ONE = 2 ** 31
+ORACLE_ABI = 2
 LEDGER = ("incoming", "toa", "atm_dir", "atm_dif", "sfc", "rr_gain", "rr_loss", "lost")
 STATS = ("photons", "collisions", "null", "scat_gas", "scat_cloud", "surface", "escape",
          "rr_kill", "rr_survive", "crossings", "absorbed", "capped")
@@ -62,6 +76,7 @@ class _Problem(ctypes.Structure):
         ("photon_offset", ctypes.c_uint64),
         ("diffuse_fraction", ctypes.c_double), ("rr_threshold", ctypes.c_double),
         ("max_iters", ctypes.c_uint32), ("nthreads", ctypes.c_int32),
+        ("sobol_entry", ctypes.c_int32),
     ]
 
 
@@ -76,6 +91,8 @@ def _load():
         if not os.path.exists(_LIB):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
+        if lib.oracle_abi() != ORACLE_ABI:
+            raise RuntimeError(f"{_LIB} is out of date: rebuild it with oracle.build()")
         P = ctypes.c_void_p
         lib.oracle_philox4x32_10_n.argtypes = [P, ctypes.c_uint64, P, ctypes.c_uint64]
         lib.oracle_philox4x64_10.argtypes = [P, P, P]
@@ -90,6 +107,9 @@ def _load():
             [ctypes.c_int32] * 3 + [ctypes.c_double] * 3 + [P, ctypes.c_double, ctypes.c_double]
             + [ctypes.c_int32] * 3)
         lib.oracle_direct_transmittance.restype = ctypes.c_double
+        lib.oracle_sobol_points_n.argtypes = [P, ctypes.c_uint32, P, P]
+        lib.oracle_owen_scramble_n.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P]
+        lib.oracle_sobol_entry.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P]
         _lib = lib
     return _lib
 
@@ -154,10 +174,35 @@ def majorant(k_ext: np.ndarray, brick) -> np.ndarray:
     return out
 
 
+def sobol_points(i) -> tuple:
+    """Unscrambled 2D Sobol points (32-bit fractions) of indices i."""
+    i = np.ascontiguousarray(i, dtype=np.uint32)
+    a = np.empty_like(i)
+    b = np.empty_like(i)
+    _load().oracle_sobol_points_n(_ptr(i), i.size, _ptr(a), _ptr(b))
+    return a, b
+
+
+def owen_scramble(v, seed: int) -> np.ndarray:
+    """Nested uniform scramble of 32-bit fractions v under a 32-bit seed."""
+    v = np.ascontiguousarray(v, dtype=np.uint32)
+    out = np.empty_like(v)
+    _load().oracle_owen_scramble_n(_ptr(v), v.size, int(seed) & 0xffffffff, _ptr(out))
+    return out
+
+
+def sobol_entry(first: int, n: int, column: int, seed: int) -> np.ndarray:
+    """Scrambled entry coordinates [n][2] (uint32 fractions of the column
+    width) of passes first .. first+n-1 of a column, as the tracer uses them."""
+    out = np.empty((n, 2), dtype=np.uint32)
+    _load().oracle_sobol_entry(int(first), int(n), int(column), int(seed), _ptr(out))
+    return out
+
+
 def trace(fields, sza: float, azimuth: float, photons: int, seed: int,
           brick=(4, 4, 4), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
           photon_offset: int = 0, max_iters: int = 1 << 24,
-          nthreads: Optional[int] = None) -> dict:
+          nthreads: Optional[int] = None, sobol_entry: bool = False) -> dict:
     """Trace `photons` photons through `fields` (a synthetic.Fields); returns
     raw uint64 tallies, ledger and stats as numpy arrays (same units and
     meaning as the GPU library's raw tallies)."""
@@ -171,7 +216,8 @@ def trace(fields, sza: float, azimuth: float, photons: int, seed: int,
                  arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
                  arrs[3].ctypes.data, alb.ctypes.data,
                  float(sza), float(azimuth), int(photons), int(seed), int(photon_offset),
-                 float(diffuse_fraction), float(rr_threshold), int(max_iters), int(nthreads))
+                 float(diffuse_fraction), float(rr_threshold), int(max_iters), int(nthreads),
+                 1 if sobol_entry else 0)
     out = {
         "abs_dir": np.zeros(grid.shape3, dtype=np.uint64),
         "abs_dif": np.zeros(grid.shape3, dtype=np.uint64),

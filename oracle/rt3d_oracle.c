@@ -42,7 +42,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORACLE_ABI 1
+#define ORACLE_ABI 2
 #define W_ONE 2147483648.0 /* 2^31: weight one */
 #define W_ONE_U 2147483648ull
 
@@ -112,6 +112,108 @@ void oracle_philox4x32_10_n(const uint32_t* ctr, uint64_t seed, uint32_t* out, u
 
 /* A 32-bit word as a uniform variate in (0,1): (u + 1/2) 2^-32. */
 static double unit_open(uint32_t u) { return ((double)u + 0.5) * (1.0 / 4294967296.0); }
+
+/* ------------------------------------------------------------------------
+ * Scrambled Sobol entry points (sec. 2.3, initialisation paragraph: rays
+ * start at the top of the domain following a scrambled Sobol sequence).
+ * Reading: photons keep the systematic column sampling, under which photon
+ * id enters column (id + o) mod ncol as that column's p-th photon with
+ * p = id div ncol (counting from 0); it takes the p-th point of the
+ * two-dimensional Sobol sequence as its position inside the column, after a
+ * nested uniform (Owen) scramble that is drawn independently per column and
+ * per run.
+ * ------------------------------------------------------------------------ */
+
+/* Dimension 1: the radical inverse of i in base 2, i.e. i's 32 bits in
+ * reverse order read as a binary fraction (times 2^32). */
+uint32_t oracle_sobol_dim1(uint32_t i)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 32; ++b)
+        if (i & (1u << b)) r |= 1u << (31 - b);
+    return r;
+}
+
+/* Dimension 2: Sobol's construction with the primitive polynomial x + 1:
+ * direction numbers m_1 = 1, m_j = 2 m_{j-1} xor m_{j-1}, i.e.
+ * v_j = m_j 2^(32-j) = v_{j-1} xor (v_{j-1} >> 1) with v_1 = 2^31; the point
+ * is the xor of v_j over the set bits j (j = 1 for the lowest) of i. */
+uint32_t oracle_sobol_dim2(uint32_t i)
+{
+    uint32_t v = 0x80000000u, r = 0;
+    for (int j = 0; j < 32; ++j) {
+        if (i & (1u << j)) r ^= v;
+        v ^= v >> 1;
+    }
+    return r;
+}
+
+/* The finaliser of MurmurHash3 (Appleby): a bijective 32-bit mix. */
+static uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* Nested uniform scramble (Owen 1995) of the 32-digit binary fraction v:
+ * digit d (d = 0 the most significant) is flipped by a random bit attached
+ * to the node of the binary tree reached by v's first d digits; the node is
+ * numbered (first d digits) | 2^d and its bit is the top bit of
+ * fmix32(node xor seed). */
+uint32_t oracle_owen_scramble(uint32_t v, uint32_t seed)
+{
+    uint32_t out = 0;
+    for (int d = 0; d < 32; ++d) {
+        uint32_t prefix = d ? v >> (32 - d) : 0u;
+        uint32_t node = prefix | (1u << d);
+        uint32_t flip = fmix32(node ^ seed) >> 31;
+        uint32_t digit = (v >> (31 - d)) & 1u;
+        out |= (digit ^ flip) << (31 - d);
+    }
+    return out;
+}
+
+/* Array forms for the tests: out[k] = dim1/dim2(i[k]) or owen(v[k], seed). */
+void oracle_sobol_points_n(const uint32_t* i, uint32_t n, uint32_t* out1, uint32_t* out2)
+{
+    for (uint32_t k = 0; k < n; ++k) {
+        out1[k] = oracle_sobol_dim1(i[k]);
+        out2[k] = oracle_sobol_dim2(i[k]);
+    }
+}
+
+void oracle_owen_scramble_n(const uint32_t* v, uint32_t n, uint32_t seed, uint32_t* out)
+{
+    for (uint32_t k = 0; k < n; ++k) out[k] = oracle_owen_scramble(v[k], seed);
+}
+
+/* Scramble seeds of column `col` under run key `key`: Philox counter
+ * (col_lo, col_hi, 0xfffffffd, 0), words 0 (x) and 1 (y). */
+static void column_scramble(const uint32_t key[2], uint64_t col, uint32_t s[2])
+{
+    uint32_t c[4] = {(uint32_t)col, (uint32_t)(col >> 32), 0xfffffffdu, 0u}, r[4];
+    oracle_philox4x32_10(c, key, r);
+    s[0] = r[0];
+    s[1] = r[1];
+}
+
+/* Scrambled entry coordinates (32-bit fractions of the column width) of
+ * passes first .. first+n-1 of column `col` in a run with Philox key
+ * `seed`: out[2k] = x, out[2k+1] = y. */
+void oracle_sobol_entry(uint64_t first, uint32_t n, uint64_t col, uint64_t seed, uint32_t* out)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, s[2];
+    column_scramble(key, col, s);
+    for (uint32_t k = 0; k < n; ++k) {
+        uint32_t p = (uint32_t)(first + k);
+        out[2 * k] = oracle_owen_scramble(oracle_sobol_dim1(p), s[0]);
+        out[2 * k + 1] = oracle_owen_scramble(oracle_sobol_dim2(p), s[1]);
+    }
+}
 
 /* ------------------------------------------------------------------------
  * Phase-function samplers (sec. 2.3, phase-function paragraph)
@@ -209,6 +311,7 @@ typedef struct {
     double diffuse_fraction, rr_threshold;
     uint32_t max_iters;
     int32_t nthreads;
+    int32_t sobol_entry; /* 1: scrambled Sobol positions inside the column */
 } oracle_problem;
 
 typedef struct {
@@ -295,6 +398,12 @@ static void trace_one(worker* W, uint64_t id)
     int32_t ic = (int32_t)(col % (uint64_t)nx), jc = (int32_t)(col / (uint64_t)nx);
     draw(W, id, 0xffffffffu, 0u, r);
     double p[3] = {(ic + unit_open(r[0])) * dx, (jc + unit_open(r[1])) * dy, W->H};
+    if (P->sobol_entry) {
+        uint32_t xy[2];
+        oracle_sobol_entry(id / W->ncol, 1u, col, P->seed, xy);
+        p[0] = (ic + unit_open(xy[0])) * dx;
+        p[1] = (jc + unit_open(xy[1])) * dy;
+    }
     double d[3];
     int direct;
     if (unit_open(r[2]) < P->diffuse_fraction) {

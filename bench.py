@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lds-majorant", type=int, default=0)
     ap.add_argument("--no-merge", action="store_true", help="one tally atomic per deposit")
+    ap.add_argument("--sobol-entry", action="store_true", help="scrambled Sobol entry positions")
+    ap.add_argument("--refill-lanes", type=int, default=0, help="idle lanes before a wave refills (0 = 16)")
     ap.add_argument("--brick", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched g-point measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -198,7 +200,8 @@ def main():
 
     def step(seed):
         raw = rt3d.trace(df, wl.sza, wl.azimuth, wl.photons, seed, brick=wl.brick, out=out, workspace=ws,
-                         timed=True, lds_majorant=args.lds_majorant, merge=not args.no_merge)
+                         timed=True, lds_majorant=args.lds_majorant, merge=not args.no_merge,
+                         sobol_entry=args.sobol_entry, refill_lanes=args.refill_lanes)
         kms = rt3d.last_trace_ms()
         fin = rt3d.finalize(grid, raw, wl.photons)
         return kms, raw["stats"].clone(), fin
@@ -224,7 +227,8 @@ def main():
     mean_kms = sum(kernel_ms) / len(kernel_ms)
     bytes_per_launch = algorithmic_bytes(tot) / args.steps
     achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
-    traffic = measured_traffic(wl.brick, wl.photons) if args.lds_majorant == 0 and not args.no_merge else None
+    traffic = measured_traffic(wl.brick, wl.photons) \
+        if args.lds_majorant == 0 and not args.no_merge and not args.sobol_entry and args.refill_lanes == 0 else None
     res = {
         "metric": METRIC,
         "value": events / wall,

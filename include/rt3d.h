@@ -70,9 +70,12 @@
  *                                                 word 2 -> cos(theta) or
  *                                                 surface mu^2, word 3 -> phi
  *   roulette at s   (id_lo, id_hi, s, 1)          word 0 -> rho
+ *   Sobol scramble  (c_lo, c_hi, 0xfffffffd, 0)   words 0,1 -> scramble
+ *                                                 seeds of column c (x, y)
  * s counts the free paths of one photon from 0.  Photon id enters column
  * c = (id + o) mod (nx*ny), cell (c mod nx, c div nx) (systematic sampling:
- * every column receives floor or ceil of photons/(nx*ny) photons).
+ * every column receives floor or ceil of photons/(nx*ny) photons), as the
+ * column's (id div (nx*ny))-th photon.
  */
 #ifndef RT3D_H
 #define RT3D_H
@@ -84,7 +87,7 @@
 extern "C" {
 #endif
 
-#define RT3D_ABI_VERSION 1
+#define RT3D_ABI_VERSION 2
 
 typedef enum {
     RT3D_OK = 0,
@@ -179,6 +182,11 @@ enum {
 #define RT3D_FLAG_NO_MERGE 0x8u   /* one tally atomic per deposit instead of
                                      merging a lane's consecutive deposits
                                      into the same cell (same results) */
+#define RT3D_FLAG_SOBOL_ENTRY 0x10u /* entry positions inside each column from
+                                     a scrambled 2D Sobol sequence (sec. 2.3,
+                                     initialisation paragraph) instead of
+                                     independent uniforms; see
+                                     rt3d_sobol_entry for the definition */
 
 typedef struct {
     /* acceleration-grid cell ("brick") in fine cells; must divide nx, ny, nz */
@@ -199,6 +207,9 @@ typedef struct {
                                 0 = automatic (unbounded with LDS majorants) */
     int32_t pool_photons;    /* photon ids a wave takes from the work queue
                                 at a time, 0 = 256 */
+    int32_t refill_lanes;    /* a wave starts new photons once at least this
+                                many of its 64 lanes are idle (or none is
+                                alive), 1..64; 0 = 16 */
 } rt3d_options;
 
 /* Several g-points in one launch (sec. 2.2: 112 shortwave quadrature points;
@@ -216,6 +227,10 @@ typedef struct {
     const float* k_cloud;
     const float* ssa_cloud;
     const float* g_cloud;
+    /* diffuse fraction of the TOD flux of each g-point, device FP32
+     * [n_gpoints] in [0,1] (e.g. from rt3d_two_stream); NULL = every g-point
+     * uses opt->diffuse_fraction */
+    const float* diffuse_fraction;
 } rt3d_batched_medium;
 
 #define RT3D_MAX_GPOINTS 256
@@ -308,6 +323,60 @@ rt3d_status rt3d_finalize(const rt3d_grid* grid, const rt3d_tallies* raw,
  * out[4*i .. 4*i+3] (device uint32), key = (seed lo, seed hi). */
 rt3d_status rt3d_philox4x32_10(const uint32_t* ctr, uint64_t seed,
                                uint32_t* out, uint32_t n, void* stream);
+
+/* Entry points of RT3D_FLAG_SOBOL_ENTRY (sec. 2.3, initialisation
+ * paragraph: rays start at the top of the domain following a scrambled
+ * Sobol sequence), for bit-level tests.  The p-th photon to enter column
+ * `column` (p counted from 0, see the counter layout above) of a run with
+ * Philox key `seed` starts at fractions (x, y) of the column's width, where
+ * x, y are the 2D Sobol point p (dimension 1: bits of p reversed; dimension
+ * 2: primitive polynomial x + 1, direction numbers v_1 = 2^31,
+ * v_j = v_{j-1} xor (v_{j-1} >> 1), xor over the set bits of p), each under
+ * Owen's nested uniform scramble: binary digit d (0 = most significant) is
+ * flipped by the top bit of fmix32(node xor s), node = (first d digits) |
+ * 2^d, fmix32 = MurmurHash3's finaliser, s = the column's scramble seed for
+ * that coordinate.  For passes first_pass .. first_pass+n-1 writes the
+ * 32-digit scrambled x, y to out[2*i], out[2*i+1] (device uint32); the tracer
+ * uses their first 24 digits.  p is taken mod 2^32. */
+rt3d_status rt3d_sobol_entry(uint64_t first_pass, uint32_t n, uint64_t column,
+                             uint64_t seed, uint32_t* out, void* stream);
+
+/* Clear-sky two-stream column for the flux entering the top of the domain
+ * (sec. 2.3, initialisation paragraph: the total incoming flux and its
+ * diffuse fraction at the domain top come from a two-stream solution of a
+ * clear-sky profile from the surface to the top of the atmosphere, so that
+ * tracing can be confined to the domain).  Readings: practical improved
+ * flux method coefficients (Zdunkowski, Welch and Korb 1980; Meador and
+ * Weaver 1980, Table 1) gamma1 = (8 - w(5 + 3g))/4, gamma2 = 3w(1 - g)/4,
+ * gamma3 = (2 - 3 mu0 g)/4, gamma4 = 1 - gamma3; homogeneous layers combined
+ * by the adding method; Lambertian surface with one albedo; near the
+ * resonance k mu0 = 1 (|1 - k^2 mu0^2| < 1e-3) the direct-beam terms of a
+ * layer are the mean of their values at mu0 (1 -+ 1e-3).
+ * n_cols independent columns (e.g. the g-points of a spectral set) of nlay
+ * layers, layer 0 at the top of the atmosphere; all arrays DEVICE FP64:
+ *   tau, ssa, g      [n_cols][nlay] optical depth, single-scattering albedo,
+ *                    asymmetry parameter (0 for Rayleigh gas);
+ *   albedo           [n_cols] surface albedo in [0,1];
+ *   flux_toa         [n_cols] flux normal to the beam at the top of the
+ *                    atmosphere, or NULL for 1;
+ *   flux_dir, flux_dn_dif, flux_up
+ *                    [n_cols][nlay+1] outputs at the levels (0 = top of the
+ *                    atmosphere): direct horizontal flux, diffuse downward
+ *                    and upward flux (also used as scratch; all required);
+ *   tod_flux         [n_cols] or NULL: direct + diffuse downward flux at
+ *                    level tod_level (the top of the ray tracer's domain);
+ *   tod_diffuse_fraction [n_cols] FP32 or NULL: its diffuse share (0 where
+ *                    the flux is 0), the input of rt3d_batched_medium.
+ * mu0 = cos(solar zenith angle) in (0, 1] (host); 0 <= tod_level <= nlay.
+ * RT3D_EINVAL on bad arguments (nothing launched).  One lane per column;
+ * asynchronous on `stream`. */
+rt3d_status rt3d_two_stream(int32_t n_cols, int32_t nlay, const double* tau,
+                            const double* ssa, const double* g,
+                            const double* albedo, double mu0,
+                            const double* flux_toa, double* flux_dir,
+                            double* flux_dn_dif, double* flux_up,
+                            int32_t tod_level, double* tod_flux,
+                            float* tod_diffuse_fraction, void* stream);
 
 #ifdef __cplusplus
 }

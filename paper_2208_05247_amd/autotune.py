@@ -2,7 +2,8 @@
 
 Picks the acceleration-grid cell ("brick") shape, the crossings a lane makes
 per loop iteration, the persistent grid size, the photon-id pool a wave takes
-per refill and the tally-merging mode from short calibration runs.  The
+per refill, how many idle lanes a wave waits for before it starts new photons
+and the tally-merging mode from short calibration runs.  The
 objective is tracing-kernel time per photon (HIP events around the kernel),
 not events/s: looser majorants inflate the event count without doing more
 useful work.  Every candidate traces the same photons through the same
@@ -29,6 +30,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rt3d", "autotun
 BRICKS = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 8, 4), (8, 8, 16), (4, 4, 8), (16, 16, 8), (16, 16, 4)]
 WALKS = [0, 1, 2, 4, 8]
 POOLS = [64, 256, 1024]
+REFILLS = [1, 4, 8, 16, 32]
 
 
 @dataclasses.dataclass
@@ -75,7 +77,7 @@ def _store_cache(path, cache):
 
 
 def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=None, pools=None,
-            grid_mults=(1,), try_merge=True):
+            grid_mults=(1,), try_merge=True, refills=None):
     """Staged coordinate search; run(opts) returns kernel ms for `sample` photons."""
     table = []
 
@@ -104,6 +106,13 @@ def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=
         if pool == 256:
             continue
         o = {**best, "pool_photons": pool}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
+    for rf in (refills or REFILLS):
+        if rf == 16:
+            continue
+        o = {**best, "refill_lanes": rf}
         ms = measure(o)
         if ms < best_ms:
             best_ms, best = ms, o

@@ -64,6 +64,49 @@ __device__ __forceinline__ float u01_open(uint32_t u) { return (float)((u >> 8) 
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// ---------------------------------------------------------------------------
+// Scrambled Sobol entry points (sec. 2.3: rays start at the top of the domain
+// following a scrambled Sobol sequence).  The p-th photon to enter a column
+// takes the p-th point of the 2D Sobol sequence, nested-uniform scrambled
+// per column and run.  Dimension 1 is the base-2 radical inverse (bit
+// reversal); dimension 2 uses the primitive polynomial x + 1, whose
+// direction numbers follow v_1 = 2^31, v_j = v_{j-1} ^ (v_{j-1} >> 1).
+__device__ __forceinline__ uint32_t sobol_dim2(uint32_t p) {
+    uint32_t v = 0x80000000u, r = 0;
+    while (p) {
+        if (p & 1u) r ^= v;
+        v ^= v >> 1;
+        p >>= 1;
+    }
+    return r;
+}
+
+// MurmurHash3's finaliser (a bijective 32-bit mix).
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Owen's nested uniform scramble of the first kDigits binary digits of v:
+// digit d is flipped by the top bit of fmix32(node ^ seed), node = (v's
+// first d digits) | 2^d numbering the binary-tree node above that digit.
+// Digit d depends only on digits before it, so the first 24 digits of the
+// 32-digit scramble are the 24-digit scramble.
+template <int kDigits>
+__device__ __forceinline__ uint32_t owen_scramble(uint32_t v, uint32_t seed) {
+    uint32_t out = 0;
+#pragma unroll 4
+    for (int d = 0; d < kDigits; ++d) {
+        const uint32_t node = (d ? v >> (32 - d) : 0u) | (1u << d);
+        out |= (((v >> (31 - d)) ^ (fmix32(node ^ seed) >> 31)) & 1u) << (31 - d);
+    }
+    return out;
+}
+
 // Henyey-Greenstein cos(theta) by inversion of its cumulative distribution.
 __device__ __forceinline__ float hg_cos(float g, float xi) {
     if (fabsf(g) < 1e-3f) return 2.0f * xi - 1.0f;
@@ -123,6 +166,7 @@ struct TraceParams {
     unsigned long long* queue;
     int ngp, nmaj, max_walk;
     uint32_t pool;   // photon ids a wave takes from the queue at a time
+    uint32_t refill; // a wave refills once this many of its lanes are idle
     int merge;       // merge consecutive deposits of a lane into one cell
     int nx, ny, nz, bx, by, bz, mx, my, mz;
     float dx, dy, dz, inv_dx, inv_dy, inv_dz;
@@ -130,6 +174,8 @@ struct TraceParams {
     float H;
     float sun_x, sun_y, sun_z;
     float diffuse_fraction;
+    const float* gp_diffuse;  // per-g-point diffuse fraction (batched), or null
+    int sobol;                // scrambled Sobol entry positions
     uint32_t rr_below;
     uint32_t max_iters;
     unsigned long long seed;  // g-point n draws with Philox key seed + n
@@ -274,9 +320,11 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
     };
 
     for (;;) {
-        // ---- refill finished lanes from the wave's pool of photon ids
+        // ---- refill finished lanes from the wave's pool of photon ids, once
+        // enough of them are idle (the emission code then runs for many
+        // lanes at once instead of for one or two) or none is alive
         const uint64_t dead = __ballot(!alive);
-        if (dead && !drained) {
+        if (dead && !drained && ((uint32_t)__popcll(dead) >= P.refill || !__ballot(alive))) {
             const uint32_t need = (uint32_t)__popcll(dead);
             const int leader = __ffsll((unsigned long long)dead) - 1;
             const unsigned long long avail = pool_end - pool_next;
@@ -310,10 +358,20 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
                     const int jc = (int)(col / (unsigned)P.nx);
                     const uint4 e = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 0u),
                                            key0(), key1());
-                    px = ((float)ic + u01(e.x)) * P.dx;
-                    py = ((float)jc + u01(e.y)) * P.dy;
+                    float fx = u01(e.x), fy = u01(e.y);
+                    if (P.sobol) {
+                        // photon id is the (id div ncol)-th to enter its column
+                        const uint32_t pass = (uint32_t)(id / P.ncol);
+                        const uint4 sc = philox(make_uint4((uint32_t)col, (uint32_t)(col >> 32), 0xfffffffdu, 0u),
+                                                key0(), key1());
+                        fx = u01(owen_scramble<24>(__builtin_bitreverse32(pass), sc.x));
+                        fy = u01(owen_scramble<24>(sobol_dim2(pass), sc.y));
+                    }
+                    px = ((float)ic + fx) * P.dx;
+                    py = ((float)jc + fy) * P.dy;
                     pz = P.H;
-                    if (u01(e.z) < P.diffuse_fraction) {
+                    const float fd = P.gp_diffuse ? P.gp_diffuse[gp] : P.diffuse_fraction;
+                    if (u01(e.z) < fd) {
                         const uint4 q = philox(make_uint4((uint32_t)id, (uint32_t)(id >> 32), 0xffffffffu, 1u),
                                                key0(), key1());
                         const float mu = sqrtf(u01_open(q.x));
@@ -724,9 +782,11 @@ __global__ void validate_kernel(const float* __restrict__ ke, const float* __res
 __global__ void validate_batched_kernel(const float* __restrict__ kg, const float* __restrict__ og, size_t ngas,
                                         const float* __restrict__ kc, const float* __restrict__ oc,
                                         const float* __restrict__ g, const float* __restrict__ alb, size_t ncell,
-                                        size_t ncol, uint32_t* flag) {
+                                        size_t ncol, const float* __restrict__ fd, int ngp, uint32_t* flag) {
     uint32_t bad = 0;
     const size_t s0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, st = (size_t)gridDim.x * blockDim.x;
+    if (fd)
+        for (size_t i = s0; i < (size_t)ngp; i += st) bad |= (fd[i] >= 0.f && fd[i] <= 1.f) ? 0u : 1u;
     for (size_t i = s0; i < ngas; i += st) {
         const float a = kg[i], b = og[i];
         bad |= (a >= 0.f && a < INFINITY && b >= 0.f && b <= 1.f) ? 0u : 1u;
@@ -754,6 +814,17 @@ __global__ void philox_kernel(const uint4* __restrict__ ctr, uint32_t k0, uint32
                               uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = philox(ctr[i], k0, k1);
+}
+
+// Entry coordinates of passes first .. first+n-1 of one column, all 32
+// digits scrambled (the tracer uses the first 24 of the same values).
+__global__ void sobol_entry_kernel(unsigned long long first, uint32_t n, unsigned long long col, uint32_t k0,
+                                   uint32_t k1, uint2* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 sc = philox(make_uint4((uint32_t)col, (uint32_t)(col >> 32), 0xfffffffdu, 0u), k0, k1);
+    const uint32_t p = (uint32_t)(first + i);
+    out[i] = make_uint2(owen_scramble<32>(__builtin_bitreverse32(p), sc.x), owen_scramble<32>(sobol_dim2(p), sc.y));
 }
 
 // ---------------------------------------------------------------------------
@@ -888,6 +959,7 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
     if (!(o.diffuse_fraction >= 0.f && o.diffuse_fraction <= 1.f)) return RT3D_EINVAL;
     if (!(o.rr_threshold >= 0.f && o.rr_threshold <= 1.f)) return RT3D_EINVAL;
     if (o.grid_blocks < 0 || o.block_threads < 0 || o.max_walk < 0 || o.pool_photons < 0) return RT3D_EINVAL;
+    if (o.refill_lanes < 0 || o.refill_lanes > 64) return RT3D_EINVAL;
     if (o.block_threads && o.block_threads != (factored ? Shape_<true>::threads : Shape_<false>::threads))
         return RT3D_EINVAL;
     unsigned long long total = 0;
@@ -959,7 +1031,9 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
     P.rr_below = (uint32_t)std::nearbyint((double)o.rr_threshold * 2147483648.0);
     P.max_iters = o.max_iters;
     P.pool = o.pool_photons > 0 ? (uint32_t)o.pool_photons : 256u;
+    P.refill = o.refill_lanes > 0 ? (uint32_t)o.refill_lanes : 16u;
     P.merge = (o.flags & RT3D_FLAG_NO_MERGE) ? 0 : 1;
+    P.sobol = (o.flags & RT3D_FLAG_SOBOL_ENTRY) ? 1 : 0;
     P.seed = seed;
     P.photons = total;
     P.photon_offset = o.photon_offset;
@@ -1135,11 +1209,13 @@ rt3d_status rt3d_trace_batched(const rt3d_grid* grid, int32_t n_gpoints, const r
     rt3d_status st = prepare(grid, n_gpoints, photons, surface_albedo, sza_deg, azimuth_deg, seed, opt, out,
                              workspace, workspace_bytes, stream, true, &L);
     if (st != RT3D_OK) return st;
+    L.P.gp_diffuse = medium->diffuse_fraction;
     hipStream_t hs = (hipStream_t)stream;
     if (L.o.flags & RT3D_FLAG_VALIDATE) {
         hipLaunchKernelGGL(validate_batched_kernel, dim3(grid_for(L.s.ncell, 256, 4096)), dim3(256), 0, hs,
                            medium->k_gas, medium->ssa_gas, (size_t)n_gpoints * L.s.nz, medium->k_cloud,
-                           medium->ssa_cloud, medium->g_cloud, surface_albedo, L.s.ncell, L.s.ncol, L.flag);
+                           medium->ssa_cloud, medium->g_cloud, surface_albedo, L.s.ncell, L.s.ncol,
+                           medium->diffuse_fraction, n_gpoints, L.flag);
         if ((st = validated(L, hs)) != RT3D_OK) return st;
     }
     if ((st = clear_outputs(L, out, hs)) != RT3D_OK) return st;
@@ -1198,6 +1274,17 @@ rt3d_status rt3d_philox4x32_10(const uint32_t* ctr, uint64_t seed, uint32_t* out
     if (n == 0) return RT3D_OK;
     hipLaunchKernelGGL(philox_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        (const uint4*)ctr, (uint32_t)seed, (uint32_t)(seed >> 32), (uint4*)out, n);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_sobol_entry(uint64_t first_pass, uint32_t n, uint64_t column, uint64_t seed, uint32_t* out,
+                             void* stream) {
+    if (!out) return RT3D_EINVAL;
+    if (n == 0) return RT3D_OK;
+    hipLaunchKernelGGL(sobol_entry_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       (unsigned long long)first_pass, n, (unsigned long long)column, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), (uint2*)out);
     HIP_TRY(hipGetLastError());
     return RT3D_OK;
 }

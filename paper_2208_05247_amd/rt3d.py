@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librt3d.so")
 
 OK, EINVAL, EDOMAIN, EDEVICE = 0, 1, 2, 3
-FLAG_ACCUMULATE, FLAG_VALIDATE, FLAG_TIME, FLAG_NO_MERGE = 0x1, 0x2, 0x4, 0x8
+FLAG_ACCUMULATE, FLAG_VALIDATE, FLAG_TIME, FLAG_NO_MERGE, FLAG_SOBOL_ENTRY = 0x1, 0x2, 0x4, 0x8, 0x10
 LEDGER = ("incoming", "toa", "atm_dir", "atm_dif", "sfc", "rr_gain", "rr_loss", "lost")
 STATS = ("photons", "collisions", "null", "scat_gas", "scat_cloud", "surface", "escape",
          "rr_kill", "rr_survive", "crossings", "absorbed", "capped")
@@ -29,7 +29,7 @@ TALLY2 = ("sfc_dir", "sfc_dif", "sfc_abs", "toa_up")
 EXPORTS = ("rt3d_abi_version", "rt3d_status_string", "rt3d_last_device_error",
            "rt3d_default_options", "rt3d_workspace_size", "rt3d_majorant_build",
            "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize", "rt3d_philox4x32_10",
-           "rt3d_workspace_size_batched", "rt3d_trace_batched")
+           "rt3d_workspace_size_batched", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream")
 MAX_GPOINTS = 256
 
 
@@ -59,12 +59,14 @@ class Options(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("max_iters", ctypes.c_uint32),
                 ("photon_offset", ctypes.c_uint64), ("grid_blocks", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("lds_majorant", ctypes.c_int32),
-                ("max_walk", ctypes.c_int32), ("pool_photons", ctypes.c_int32)]
+                ("max_walk", ctypes.c_int32), ("pool_photons", ctypes.c_int32),
+                ("refill_lanes", ctypes.c_int32)]
 
 
 class BatchedMedium(ctypes.Structure):
     _fields_ = [("k_gas", ctypes.c_void_p), ("ssa_gas", ctypes.c_void_p), ("k_cloud", ctypes.c_void_p),
-                ("ssa_cloud", ctypes.c_void_p), ("g_cloud", ctypes.c_void_p)]
+                ("ssa_cloud", ctypes.c_void_p), ("g_cloud", ctypes.c_void_p),
+                ("diffuse_fraction", ctypes.c_void_p)]
 
 
 _lib = None
@@ -101,10 +103,13 @@ def load(path: str = LIB_PATH):
     lib.rt3d_finalize.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(TalliesStruct), ctypes.c_uint64, P,
                                   ctypes.c_double, P, P, P, P, P, P, P]
     lib.rt3d_philox4x32_10.argtypes = [P, ctypes.c_uint64, P, ctypes.c_uint32, P]
+    lib.rt3d_sobol_entry.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
+    lib.rt3d_two_stream.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_double, P, P, P, P,
+                                    ctypes.c_int32, P, P, P]
     for name in ("rt3d_majorant_build", "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize",
-                 "rt3d_philox4x32_10", "rt3d_trace_batched"):
+                 "rt3d_philox4x32_10", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream"):
         getattr(lib, name).restype = ctypes.c_int
-    if lib.rt3d_abi_version() != 1:
+    if lib.rt3d_abi_version() != 2:
         raise RuntimeError("librt3d.so ABI version mismatch")
     _lib = lib
     return lib
@@ -161,7 +166,7 @@ class DeviceFields:
 
 def options(brick=(8, 8, 8), diffuse_fraction=0.0, rr_threshold=0.5, flags=0, max_iters=0,
             photon_offset=0, grid_blocks=0, block_threads=0, lds_majorant=0, max_walk=0,
-            pool_photons=0) -> Options:
+            pool_photons=0, refill_lanes=0) -> Options:
     o = Options()
     load().rt3d_default_options(ctypes.byref(o))
     o.brick_x, o.brick_y, o.brick_z = (int(b) for b in brick)
@@ -175,6 +180,7 @@ def options(brick=(8, 8, 8), diffuse_fraction=0.0, rr_threshold=0.5, flags=0, ma
     o.lds_majorant = int(lds_majorant)
     o.max_walk = int(max_walk)
     o.pool_photons = int(pool_photons)
+    o.refill_lanes = int(refill_lanes)
     return o
 
 
@@ -209,7 +215,8 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
           brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
           photon_offset: int = 0, accumulate: bool = False, validate: bool = False, timed: bool = False,
           max_iters: int = 0, grid_blocks: int = 0, lds_majorant: int = 0, max_walk: int = 0,
-          pool_photons: int = 0, merge: bool = True, out: Optional[dict] = None,
+          pool_photons: int = 0, refill_lanes: int = 0, merge: bool = True, sobol_entry: bool = False,
+          out: Optional[dict] = None,
           workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
     """rt3d_trace: raw uint64 tallies (int64 tensors) of `photons` photons."""
     lib = load()
@@ -217,9 +224,10 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
     for n in ("k_ext", "k_ext_cloud", "ssa", "g", "albedo"):
         _require_device(getattr(df, n), n, torch.float32)
     flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
-            (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE)
+            (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, photon_offset, grid_blocks,
-                  lds_majorant=lds_majorant, max_walk=max_walk, pool_photons=pool_photons)
+                  lds_majorant=lds_majorant, max_walk=max_walk, pool_photons=pool_photons,
+                  refill_lanes=refill_lanes)
     gs = grid_struct(grid)
     nws = workspace_size(grid, opt)
     if workspace is None:
@@ -271,9 +279,13 @@ def workspace_size_batched(grid, n_gpoints: int, opt: Options) -> int:
 def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: Sequence[int], seed: int, *,
                   brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
                   accumulate: bool = False, validate: bool = False, timed: bool = False, max_iters: int = 0,
-                  grid_blocks: int = 0, max_walk: int = 0, pool_photons: int = 0, merge: bool = True,
+                  grid_blocks: int = 0, max_walk: int = 0, pool_photons: int = 0, refill_lanes: int = 0,
+                  merge: bool = True,
+                  sobol_entry: bool = False, gpoint_diffuse: Optional[torch.Tensor] = None,
                   out: Optional[dict] = None, workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
-    """rt3d_trace_batched: broadband raw tallies of all g-points in one launch."""
+    """rt3d_trace_batched: broadband raw tallies of all g-points in one launch.
+    gpoint_diffuse: FP32 device [ngp] diffuse fraction per g-point (e.g.
+    two_stream()'s "tod_diffuse_fraction"), else diffuse_fraction for all."""
     lib = load()
     grid = dm.grid
     for n in ("k_gas", "ssa_gas", "k_cloud", "ssa_cloud", "g_cloud", "albedo"):
@@ -281,10 +293,14 @@ def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: 
     ngp = dm.n_gpoints
     if len(photons) != ngp:
         raise ValueError("one photon count per g-point")
+    if gpoint_diffuse is not None:
+        _require_device(gpoint_diffuse, "gpoint_diffuse", torch.float32)
+        if gpoint_diffuse.numel() != ngp:
+            raise ValueError("gpoint_diffuse needs one value per g-point")
     flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
-            (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE)
+            (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, 0, grid_blocks, max_walk=max_walk,
-                  pool_photons=pool_photons)
+                  pool_photons=pool_photons, refill_lanes=refill_lanes)
     gs = grid_struct(grid)
     nws = workspace_size_batched(grid, ngp, opt)
     if workspace is None:
@@ -292,7 +308,8 @@ def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: 
     if out is None:
         out = alloc_tallies(grid, dm.k_cloud.device)
     med = BatchedMedium(dm.k_gas.data_ptr(), dm.ssa_gas.data_ptr(), dm.k_cloud.data_ptr(),
-                        dm.ssa_cloud.data_ptr(), dm.g_cloud.data_ptr())
+                        dm.ssa_cloud.data_ptr(), dm.g_cloud.data_ptr(),
+                        gpoint_diffuse.data_ptr() if gpoint_diffuse is not None else None)
     counts = np.ascontiguousarray(np.asarray(photons, dtype=np.uint64))
     ts = tallies_struct(out)
     st = lib.rt3d_trace_batched(ctypes.byref(gs), ngp, ctypes.byref(med), counts.ctypes.data_as(ctypes.c_void_p),
@@ -350,6 +367,42 @@ def philox4x32_10(ctr: torch.Tensor, seed: int, stream=None) -> torch.Tensor:
     out = torch.empty_like(ctr)
     _check(load().rt3d_philox4x32_10(ctypes.c_void_p(ctr.data_ptr()), int(seed), ctypes.c_void_p(out.data_ptr()),
                                      int(ctr.shape[0]), _stream(stream)), "rt3d_philox4x32_10")
+    return out
+
+
+def sobol_entry(first_pass: int, n: int, column: int, seed: int, device="cuda", stream=None) -> torch.Tensor:
+    """rt3d_sobol_entry: scrambled entry coordinates [n, 2] (int32 device
+    tensor holding the uint32 fractions of the column width)."""
+    out = torch.empty((n, 2), dtype=torch.int32, device=device)
+    _check(load().rt3d_sobol_entry(int(first_pass), int(n), int(column), int(seed),
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream)), "rt3d_sobol_entry")
+    return out
+
+
+def two_stream(tau: torch.Tensor, ssa: torch.Tensor, g: torch.Tensor, albedo: torch.Tensor, mu0: float,
+               tod_level: int, flux_toa: Optional[torch.Tensor] = None, stream=None) -> dict:
+    """rt3d_two_stream over columns [n_cols, nlay] (FP64 device tensors,
+    layer 0 at the top of the atmosphere): level fluxes "dir", "dn_dif", "up"
+    [n_cols, nlay+1] and, at level tod_level, "tod_flux" (FP64) and
+    "tod_diffuse_fraction" (FP32)."""
+    for name, t in (("tau", tau), ("ssa", ssa), ("g", g), ("albedo", albedo)):
+        _require_device(t, name, torch.float64)
+    if tau.dim() != 2 or ssa.shape != tau.shape or g.shape != tau.shape or albedo.numel() != tau.shape[0]:
+        raise ValueError("tau, ssa, g must be [n_cols, nlay] and albedo [n_cols]")
+    if flux_toa is not None:
+        _require_device(flux_toa, "flux_toa", torch.float64)
+        if flux_toa.numel() != tau.shape[0]:
+            raise ValueError("flux_toa must have n_cols entries")
+    nc, nl = int(tau.shape[0]), int(tau.shape[1])
+    dev = tau.device
+    out = {k: torch.empty((nc, nl + 1), dtype=torch.float64, device=dev) for k in ("dir", "dn_dif", "up")}
+    out["tod_flux"] = torch.empty(nc, dtype=torch.float64, device=dev)
+    out["tod_diffuse_fraction"] = torch.empty(nc, dtype=torch.float32, device=dev)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+    _check(load().rt3d_two_stream(nc, nl, ptr(tau), ptr(ssa), ptr(g), ptr(albedo), float(mu0), ptr(flux_toa),
+                                  ptr(out["dir"]), ptr(out["dn_dif"]), ptr(out["up"]), int(tod_level),
+                                  ptr(out["tod_flux"]), ptr(out["tod_diffuse_fraction"]), _stream(stream)),
+           "rt3d_two_stream")
     return out
 
 

@@ -290,6 +290,34 @@ def gpoint_set(grid: Grid, n_gp: int, rng: np.random.Generator, tau_range=(1e-3,
     return kg, og, w
 
 
+def clear_sky_columns(medium: "BatchedMedium", n_above: int = 32, top: float = 60000.0,
+                      scale_height: float = 8000.0):
+    """Clear-sky columns of the g-points from the top of the atmosphere to
+    the surface, the input of the two-stream calculation of the flux at the
+    top of the domain: n_above equal layers between the domain top H and
+    `top` continue each g-point's gas profile as k(z) = k_top exp(-(z - z_top)
+    / scale_height) (k_top, z_top: the domain's top level and its centre)
+    with that level's single-scattering albedo; below them the domain's own
+    gas levels.  Returns FP64 (tau, ssa, g) [ngp][n_above + nz] with layer 0
+    at the top of the atmosphere (g = 0: Rayleigh gas); the top of the domain
+    is level n_above."""
+    grid = medium.grid
+    H = grid.nz * grid.dz
+    z_top = H - 0.5 * grid.dz
+    edges = np.linspace(top, H, n_above + 1)            # downward
+    kg = medium.k_gas.astype(np.float64)
+    og = medium.ssa_gas.astype(np.float64)
+    k_top = kg[:, -1:]
+    # exact layer integrals of k_top exp(-(z - z_top)/Hs) between the edges
+    up = np.exp(-(edges[:-1] - z_top) / scale_height)
+    lo = np.exp(-(edges[1:] - z_top) / scale_height)
+    tau_above = k_top * scale_height * (lo - up)[None, :]
+    tau_dom = (kg * grid.dz)[:, ::-1]                   # top level first
+    tau = np.concatenate([tau_above, tau_dom], axis=1)
+    ssa = np.concatenate([np.repeat(og[:, -1:], n_above, axis=1), og[:, ::-1]], axis=1)
+    return np.ascontiguousarray(tau), np.ascontiguousarray(ssa), np.zeros_like(tau)
+
+
 def batched_cumulus(seed: int = 1, nx: int = 512, ny: int = 512, nz: int = 96, dx: float = 50.0,
                     dz: float = 32.0, n_gp: int = 112, photons: int = 1 << 28, n_blobs=None,
                     sza: float = 45.0, brick=(8, 8, 8), albedo=0.2) -> BatchedWorkload:

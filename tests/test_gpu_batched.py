@@ -79,7 +79,8 @@ def test_batched_equals_sum_of_single_gpoints(rt3d):
 
 
 @pytest.mark.parametrize("kw", [dict(max_walk=1), dict(max_walk=3), dict(pool_photons=64),
-                                dict(pool_photons=1024), dict(merge=False), dict(grid_blocks=5)])
+                                dict(pool_photons=1024), dict(merge=False), dict(grid_blocks=5),
+                                dict(refill_lanes=1), dict(refill_lanes=64), dict(refill_lanes=7)])
 def test_launch_options_do_not_change_tallies(rt3d, kw):
     wl = syn.small_cumulus()
     df = rt3d.DeviceFields.from_host(wl.fields)

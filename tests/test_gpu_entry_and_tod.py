@@ -1,0 +1,293 @@
+"""Flux entering the top of the domain: the clear-sky two-stream column
+(rt3d_two_stream) and its per-g-point diffuse fraction in the batched
+launch; scrambled-Sobol entry positions (RT3D_FLAG_SOBOL_ENTRY).
+
+Bit-exact: the Sobol entry coordinates against the oracle, traced vacuum
+landing columns photon by photon, one batched launch with per-g-point
+diffuse fractions against single-g-point launches.  FP64: the two-stream
+fluxes against the oracle within 1e-10 relative (independent exp / expm1
+implementations, amplified by the adding recursion).  Statistical: traced
+tallies with Sobol entry and with two-stream TOD inputs against the
+oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from oracle import two_stream as ots  # noqa: E402
+from mc_stats import compare_batches  # noqa: E402
+from paper_2208_05247_amd import synthetic as syn  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+W1 = 2 ** 31
+ARRAYS = ("abs_dir", "abs_dif", "sfc_dir", "sfc_dif", "sfc_abs", "toa_up")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rt3d():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device")
+    from paper_2208_05247_amd import rt3d as lib
+    lib.load()
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# Scrambled Sobol entry
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("first,n,col,seed", [(0, 4096, 0, 1), (1 << 20, 1000, 65535, 0xdeadbeefcafebabe),
+                                              (2 ** 32 - 10, 20, 2 ** 33 + 5, 7), (3, 1, 12, 0)])
+def test_sobol_entry_bit_exact(rt3d, first, n, col, seed):
+    g = rt3d.sobol_entry(first, n, col, seed).cpu().numpy().view(np.uint32)
+    o = oracle.sobol_entry(first, n, col, seed)
+    assert np.array_equal(g, o)
+
+
+@pytest.mark.parametrize("per,sza,az,seed", [(1, 37.0, 61.0, 5), (16, 52.0, 200.0, 6), (48, 20.0, 300.0, 7)])
+def test_sobol_vacuum_landing_columns(rt3d, per, sza, az, seed):
+    """Photon id enters column (id + o) mod ncol as its (id div ncol)-th
+    photon at the scrambled Sobol point of that pass (first 24 digits, as
+    the FP32 position uses them); in vacuum it lands where that point,
+    shifted along the sun beam, falls.  The traced surface tallies match the
+    prediction photon for photon (a landing point within FP32 rounding of a
+    column edge may fall either way: at most two such photons)."""
+    nx, ny, nz, d = 8, 4, 2, 50.0
+    grid = syn.Grid(nx, ny, nz, d, d, d)
+    f = syn.uniform_fields(grid, 0.0, 0.0, 0.0, 0.0, albedo=0.0)
+    df = rt3d.DeviceFields.from_host(f)
+    ncol = nx * ny
+    n = per * ncol + 3
+    raw = rt3d.to_host(rt3d.trace(df, sza, az, n, seed, brick=(1, 1, 1), sobol_entry=True))
+    o = int(oracle.philox4x32_10(np.array([[0, 0, 0xfffffffe, 0]], dtype=np.uint32), seed)[0, 0]) * ncol >> 32
+    th, ph = np.radians(sza), np.radians(az)
+    H = nz * d
+    sx, sy = -np.sin(th) * np.sin(ph) / np.cos(th) * H, -np.sin(th) * np.cos(ph) / np.cos(th) * H
+    want = np.zeros((ny, nx), dtype=np.int64)
+    for pid in range(n):
+        col = (pid + o) % ncol
+        ic, jc = col % nx, col // nx
+        xy = oracle.sobol_entry(pid // ncol, 1, col, seed)[0]
+        fx, fy = (int(xy[0]) >> 8) * 2.0 ** -24, (int(xy[1]) >> 8) * 2.0 ** -24
+        x, y = (ic + fx) * d + sx, (jc + fy) * d + sy
+        want[int(np.floor(y / d)) % ny, int(np.floor(x / d)) % nx] += 1
+    got = raw["sfc_dir"].astype(np.int64) // W1
+    assert got.sum() == n
+    assert np.abs(got - want).sum() <= 4, (got, want)
+
+
+def test_sobol_parity_small_cumulus(rt3d):
+    """32x32x64 cumulus, 32 batches of 2^14 photons with Sobol entry, GPU vs
+    oracle (independent seeds), 4-SE rule per cell."""
+    wl = syn.small_cumulus()
+    df = rt3d.DeviceFields.from_host(wl.fields)
+    B, per = 32, 1 << 14
+    g = {k: [] for k in ARRAYS}
+    o = {k: [] for k in ARRAYS}
+    for b in range(B):
+        raw = rt3d.trace(df, wl.sza, wl.azimuth, per, 100 + b, brick=wl.brick, sobol_entry=True)
+        fin = rt3d.finalize(wl.fields.grid, raw, per)
+        r = oracle.trace(wl.fields, wl.sza, wl.azimuth, per, 900 + b, brick=wl.brick, sobol_entry=True)
+        ofin = oracle.finalize(r, wl.fields.grid, per)
+        for k in ARRAYS:
+            g[k].append(fin[k].double().cpu().numpy())
+            o[k].append(ofin[k])
+    for k in ARRAYS:
+        frac, n_dense, _, dense, z = compare_batches(np.stack(g[k]), np.stack(o[k]))
+        say("sobol parity", k, round(frac, 5), n_dense)
+        assert frac >= 0.998, k
+
+
+def test_sobol_lowers_column_noise_on_gpu(rt3d):
+    """Vacuum, slanted sun, 1024 photons per column: the per-column noise of
+    the direct surface irradiance with Sobol entry is below a tenth of that
+    with independent entry points (both means exactly 1)."""
+    grid = syn.Grid(16, 16, 4, 100.0, 100.0, 100.0)
+    f = syn.uniform_fields(grid, 0.0, 0.0, 0.0, 0.0, albedo=0.0)
+    df = rt3d.DeviceFields.from_host(f)
+    sd = {}
+    for sob in (False, True):
+        vals = []
+        for s in range(8):
+            raw = rt3d.to_host(rt3d.trace(df, 40.0, 35.0, 256 * 1024, 100 + s, brick=(4, 4, 4), sobol_entry=sob))
+            vals.append(raw["sfc_dir"].astype(np.float64) / (1024 * W1))
+        vals = np.array(vals)
+        assert vals.mean() == pytest.approx(1.0, abs=1e-12)
+        sd[sob] = vals.std(axis=0, ddof=1).mean()
+    say("column noise philox", sd[False], "sobol", sd[True])
+    assert sd[True] < 0.1 * sd[False]
+
+
+# ---------------------------------------------------------------------------
+# Two-stream TOD column
+# ---------------------------------------------------------------------------
+
+def columns(rng, ncol, nlay, mu0):
+    tau = np.exp(rng.uniform(np.log(1e-4), np.log(3.0), (ncol, nlay)))
+    ssa = rng.uniform(0.0, 1.0, (ncol, nlay))
+    ssa[:, ::7] = 1.0
+    ssa[:, 3::11] = 0.0
+    g = rng.uniform(-0.5, 0.9, (ncol, nlay))
+    g[::2] = 0.0
+    # resonant layers (k mu0 = 1 for w = 0.5, g = 0) in some columns
+    ssa[5, 10:14], g[5, 10:14] = 0.5, 0.0
+    ssa[9, :], g[9, :] = 0.5, 0.0
+    alb = rng.uniform(0.0, 1.0, ncol)
+    alb[0], alb[1] = 0.0, 1.0
+    ftoa = rng.uniform(100.0, 1400.0, ncol)
+    return tau, ssa, g, alb, ftoa
+
+
+def test_two_stream_parity(rt3d):
+    """112 columns x 150 layers (optical depth 1e-4..3 per layer, conservative,
+    pure-absorbing and resonant layers, black and white surfaces) against the
+    FP64 oracle at every level, and the TOD flux / diffuse fraction."""
+    g1, g2, _, _ = ots.gammas(0.5, 0.0, 0.5)
+    mu0 = 1.0 / float(np.sqrt((g1 - g2) * (g1 + g2)))
+    rng = np.random.default_rng(42)
+    ncol, nlay, tod = 112, 150, 37
+    tau, ssa, g, alb, ftoa = columns(rng, ncol, nlay, mu0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    out = rt3d.two_stream(dev(tau), dev(ssa), dev(g), dev(alb), mu0, tod, flux_toa=dev(ftoa))
+    worst = 0.0
+    for c in range(ncol):
+        S, D, U = ots.column(tau[c], ssa[c], g[c], mu0, alb[c], flux_toa=ftoa[c])
+        for name, ref in (("dir", S), ("dn_dif", D), ("up", U)):
+            got = out[name][c].cpu().numpy()
+            scale = ftoa[c] * mu0
+            err = np.abs(got - ref) / (np.abs(ref) + 1e-12 * scale)
+            worst = max(worst, float(err.max()))
+            assert np.allclose(got, ref, rtol=1e-10, atol=1e-13 * scale), (c, name)
+        tot = S[tod] + D[tod]
+        assert out["tod_flux"][c].item() == pytest.approx(tot, rel=1e-10)
+        assert out["tod_diffuse_fraction"][c].item() == pytest.approx(np.float32(D[tod] / tot), rel=2e-7)
+    say("two-stream worst relative error", worst)
+
+
+def test_two_stream_degenerate_columns(rt3d):
+    """One layer; an empty-sky column (tau 0: all direct, nothing diffuse);
+    the TOD at the top of the atmosphere (fraction 0) and at the surface."""
+    tau = np.array([[0.0, 0.0, 0.0], [0.5, 0.0, 2.0]])
+    ssa = np.array([[1.0, 1.0, 1.0], [0.9, 0.0, 1.0]])
+    g = np.zeros_like(tau)
+    alb = np.array([0.3, 0.0])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    for tod in (0, 3):
+        out = rt3d.two_stream(dev(tau), dev(ssa), dev(g), dev(alb), 0.6, tod)
+        for c in range(2):
+            S, D, U = ots.column(tau[c], ssa[c], g[c], 0.6, alb[c])
+            assert np.allclose(out["dir"][c].cpu().numpy(), S, rtol=1e-12, atol=1e-15)
+            assert np.allclose(out["dn_dif"][c].cpu().numpy(), D, rtol=1e-10, atol=1e-15)
+            assert np.allclose(out["up"][c].cpu().numpy(), U, rtol=1e-10, atol=1e-15)
+        fd = out["tod_diffuse_fraction"].cpu().numpy()
+        assert fd[0] == 0.0
+        if tod == 0:
+            assert fd[1] == 0.0
+    one = rt3d.two_stream(dev(tau[:1, :1]), dev(ssa[:1, :1]), dev(g[:1, :1]), dev(alb[:1]), 1.0, 1)
+    assert one["tod_flux"][0].item() == pytest.approx(1.0, rel=1e-14)
+    with pytest.raises(rt3d.Rt3dError):
+        rt3d.two_stream(dev(tau), dev(ssa), dev(g), dev(alb), 0.6, 4)
+
+
+# ---------------------------------------------------------------------------
+# Per-g-point diffuse entry in the batched launch
+# ---------------------------------------------------------------------------
+
+def small_batch(n_gp=5, photons=1 << 15, seed=3):
+    return syn.batched_cumulus(seed=seed, nx=32, ny=32, nz=32, dx=50.0, dz=50.0, n_gp=n_gp,
+                               photons=photons, n_blobs=6, brick=(4, 4, 4))
+
+
+def test_gpoint_diffuse_equals_single_launches(rt3d):
+    """One launch with a diffuse fraction per g-point = the sum of one-g-point
+    launches each given its fraction as the scalar option (keys seed + n),
+    bitwise; also with Sobol entry."""
+    wl = small_batch()
+    m = wl.medium
+    counts = [int(c) for c in wl.photons]
+    fd = np.array([0.0, 0.3, 1.0, 0.55, 0.9], dtype=np.float32)
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    for sob in (False, True):
+        full = rt3d.to_host(rt3d.trace_batched(dm, wl.sza, wl.azimuth, counts, 77, brick=wl.brick,
+                                               gpoint_diffuse=torch.from_numpy(fd).cuda(), sobol_entry=sob))
+        acc = None
+        for n in range(m.n_gpoints):
+            if counts[n] == 0:
+                continue
+            one = rt3d.DeviceBatchedMedium(m.grid, dm.k_gas[n:n + 1].contiguous(), dm.ssa_gas[n:n + 1].contiguous(),
+                                           dm.k_cloud, dm.ssa_cloud, dm.g_cloud, dm.albedo)
+            h = rt3d.to_host(rt3d.trace_batched(one, wl.sza, wl.azimuth, [counts[n]], 77 + n, brick=wl.brick,
+                                                diffuse_fraction=float(fd[n]), sobol_entry=sob))
+            acc = h if acc is None else {k: acc[k] + h[k] for k in ARRAYS + ("ledger", "stats")}
+        for k in ARRAYS + ("ledger", "stats"):
+            assert np.array_equal(acc[k], full[k]), (k, sob)
+
+
+def test_gpoint_diffuse_validation(rt3d):
+    wl = small_batch(n_gp=3, photons=1 << 12)
+    dm = rt3d.DeviceBatchedMedium.from_host(wl.medium)
+    bad = torch.tensor([0.1, 1.5, 0.2], dtype=torch.float32, device="cuda")
+    with pytest.raises(rt3d.Rt3dError) as e:
+        rt3d.trace_batched(dm, wl.sza, wl.azimuth, [int(c) for c in wl.photons], 1, brick=wl.brick,
+                           gpoint_diffuse=bad, validate=True)
+    assert e.value.status == rt3d.EDOMAIN
+
+
+def test_two_stream_tod_end_to_end_parity(rt3d):
+    """The paper's set-up: clear-sky columns of every g-point (the domain's
+    gas levels plus 32 layers up to 60 km continuing their profiles) give
+    each g-point's TOD flux and diffuse fraction (GPU two-stream vs oracle);
+    photons go to g-points in proportion to the TOD flux; the batched launch
+    with per-g-point diffuse fractions agrees with the oracle traced per
+    g-point with the same fractions, cell by cell (32 batches)."""
+    wl = small_batch(n_gp=6, photons=1 << 15, seed=5)
+    m = wl.medium
+    tau, ssa, g = syn.clear_sky_columns(m, n_above=32)
+    mu0 = float(np.cos(np.radians(wl.sza)))
+    alb = np.full(m.n_gpoints, float(m.albedo.mean()))
+    ftoa = 1361.0 * m.weights
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    ts_out = rt3d.two_stream(dev(tau), dev(ssa), dev(g), dev(alb), mu0, 32, flux_toa=dev(ftoa))
+    fd = ts_out["tod_diffuse_fraction"]
+    ftod = ts_out["tod_flux"].cpu().numpy()
+    for n in range(m.n_gpoints):
+        tot, frac = ots.top_of_domain(tau[n], ssa[n], g[n], mu0, alb[n], 32, flux_toa=ftoa[n])
+        assert ftod[n] == pytest.approx(tot, rel=1e-10)
+        assert fd[n].item() == pytest.approx(np.float32(frac), rel=2e-7)
+    say("TOD flux", np.round(ftod, 3), "diffuse fraction", np.round(fd.cpu().numpy(), 4))
+    rng = np.random.default_rng(8)
+    counts = [int(c) for c in rng.multinomial(1 << 15, ftod / ftod.sum())]
+    total = sum(counts)
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    fields = [m.fields_of(n) for n in range(m.n_gpoints)]
+    fdh = fd.cpu().numpy()
+    B = 32
+    gpu = {k: [] for k in ARRAYS}
+    ora = {k: [] for k in ARRAYS}
+    for b in range(B):
+        raw = rt3d.trace_batched(dm, wl.sza, wl.azimuth, counts, 1000 * b + 1, brick=wl.brick, gpoint_diffuse=fd)
+        fin = rt3d.finalize(m.grid, raw, total)
+        for k in ARRAYS:
+            gpu[k].append(fin[k].double().cpu().numpy())
+        acc = None
+        for n, f in enumerate(fields):
+            if counts[n] == 0:
+                continue
+            r = oracle.trace(f, wl.sza, wl.azimuth, counts[n], 700000 + 1000 * b + n, brick=wl.brick,
+                             diffuse_fraction=float(fdh[n]))
+            acc = r if acc is None else {k: acc[k] + r[k] for k in ARRAYS}
+        ofin = oracle.finalize(acc, m.grid, total)
+        for k in ARRAYS:
+            ora[k].append(ofin[k])
+    for k in ARRAYS:
+        frac, n_dense, _, dense, z = compare_batches(np.stack(gpu[k]), np.stack(ora[k]))
+        say("tod parity", k, round(frac, 5), n_dense)
+        assert frac >= 0.998, k

@@ -41,7 +41,7 @@ def test_exports_match_header(lib):
 
 
 def test_abi_and_strings(lib):
-    assert lib.rt3d_abi_version() == 1
+    assert lib.rt3d_abi_version() == 2
     for s in range(4):
         assert lib.rt3d_status_string(s)
     assert lib.rt3d_status_string(99) == b"unknown status"
@@ -95,6 +95,15 @@ def test_einval_before_any_launch(lib):
     assert lib.rt3d_philox4x32_10(None, 1, None, 4, None) == rt3d.EINVAL
     ms = ctypes.c_float()
     assert lib.rt3d_last_trace_ms(ctypes.byref(ms)) == rt3d.EINVAL
+    assert lib.rt3d_sobol_entry(0, 4, 0, 1, None, None) == rt3d.EINVAL
+    ts = lib.rt3d_two_stream
+    assert ts(0, 5, None, None, None, None, 0.5, None, None, None, None, 0, None, None, None) == rt3d.EINVAL
+    fake = ctypes.c_void_p(256)  # never dereferenced: the host checks reject first
+    args = [fake] * 4
+    assert ts(2, 5, *args, 0.0, None, fake, fake, fake, 0, None, None, None) == rt3d.EINVAL   # mu0 = 0
+    assert ts(2, 5, *args, 1.5, None, fake, fake, fake, 0, None, None, None) == rt3d.EINVAL   # mu0 > 1
+    assert ts(2, 5, *args, 0.5, None, fake, fake, fake, 6, None, None, None) == rt3d.EINVAL   # level > nlay
+    assert ts(2, 5, *args, 0.5, None, None, fake, fake, 0, None, None, None) == rt3d.EINVAL   # no output
 
 
 def test_product_path_has_no_fallback():

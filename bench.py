@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -157,6 +159,75 @@ def batched_measurement(steps: int) -> dict:
             "speedup_vs_separate_launches": sep / wall}
 
 
+def entry_measurement(reps: int = 4) -> dict:
+    """Scrambled-Sobol against independent entry positions at equal photon
+    counts on the benchmark field: relative RMS error (the reference's own
+    noise removed, reference = two independent halves of 1024 photons per
+    column each) of the direct and diffuse surface irradiance and of the
+    absorbed power per cell, at 16, 64 and 256 photons per column (RMS of
+    `reps` seeds)."""
+    import torch
+    from paper_2208_05247_amd import rt3d
+    from paper_2208_05247_amd import synthetic as syn
+    from paper_2208_05247_amd.experiment import eps_against
+
+    wl = syn.les_cumulus()
+    grid = wl.fields.grid
+    df = rt3d.DeviceFields.from_host(wl.fields)
+    out = rt3d.alloc_tallies(grid)
+    ws = rt3d.alloc_workspace(rt3d.workspace_size(grid, rt3d.options(brick=wl.brick)))
+
+    def run(photons, seed, sob):
+        raw = rt3d.trace(df, wl.sza, wl.azimuth, photons, seed, brick=wl.brick, out=out, workspace=ws,
+                         sobol_entry=sob)
+        fin = rt3d.finalize(grid, raw, photons)
+        return {"sfc_dir": fin["sfc_dir"].double(), "sfc_dif": fin["sfc_dif"].double(),
+                "absorbed": (fin["abs_dir"].double() + fin["abs_dif"].double())}
+
+    ncol = grid.nx * grid.ny
+    ref_a = run(1024 * ncol, 90001, False)
+    ref_b = run(1024 * ncol, 90002, False)
+    res = {"workload": "les_cumulus_256x256x128", "reference_photons_per_column": 2048, "seeds": reps}
+    for per in (16, 64, 256):
+        row = {}
+        for sob in (False, True):
+            acc = {k: 0.0 for k in ref_a}
+            for r in range(reps):
+                h = run(per * ncol, 1000 * per + r, sob)
+                for k in acc:
+                    acc[k] += eps_against(h[k], ref_a[k], ref_b[k]) ** 2 / reps
+            row["sobol" if sob else "independent"] = {k: v ** 0.5 for k, v in acc.items()}
+        row["error_ratio"] = {k: row["sobol"][k] / row["independent"][k] for k in ref_a}
+        res[str(per)] = row
+    torch.cuda.synchronize()
+    return res
+
+
+def two_stream_measurement(reps: int = 20) -> dict:
+    """Kernel time of the clear-sky two-stream TOD column for 112 g-points
+    (32 layers above the domain + the 96 levels of the batched field)."""
+    import torch
+    from paper_2208_05247_amd import rt3d
+    from paper_2208_05247_amd import synthetic as syn
+
+    wl = syn.batched_cumulus()
+    tau, ssa, g = syn.clear_sky_columns(wl.medium, n_above=32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    t, w, a = dev(tau), dev(ssa), dev(g)
+    alb = dev(np.full(tau.shape[0], 0.2))
+    mu0 = float(np.cos(np.radians(wl.sza)))
+    rt3d.two_stream(t, w, a, alb, mu0, 32)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        o = rt3d.two_stream(t, w, a, alb, mu0, 32)
+    e1.record()
+    torch.cuda.synchronize()
+    fd = o["tod_diffuse_fraction"].cpu().numpy()
+    return {"columns": int(tau.shape[0]), "layers": int(tau.shape[1]), "ms_per_call": e0.elapsed_time(e1) / reps,
+            "diffuse_fraction_range": [float(fd.min()), float(fd.max())]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +330,8 @@ def main():
     }
     if not args.no_batched:
         res["batched"] = batched_measurement(max(1, min(args.steps, 3)))
+        res["sobol_entry"] = entry_measurement()
+        res["two_stream_tod"] = two_stream_measurement()
     res["time_to_5pct_heating_rms"] = time_to_5pct()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl)

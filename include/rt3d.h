@@ -12,7 +12,10 @@
  *     the paragraph on required inputs);
  *   - photons enter at the top of the domain (TOD) along the solar beam or,
  *     with probability equal to the diffuse fraction, isotropically
- *     downwards (sec. 2.3, initialisation paragraph);
+ *     downwards, at positions from independent uniforms or a scrambled
+ *     Sobol sequence; the TOD flux and diffuse fraction come from a
+ *     clear-sky two-stream column (sec. 2.3, initialisation paragraph;
+ *     RT3D_FLAG_SOBOL_ENTRY, rt3d_two_stream);
  *   - null-collision tracking on a one-level coarse acceleration grid whose
  *     cells hold the maximum fine-cell extinction (sec. 2.3, acceleration
  *     grid paragraph);

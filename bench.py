@@ -239,6 +239,7 @@ def main():
     ap.add_argument("--no-merge", action="store_true", help="one tally atomic per deposit")
     ap.add_argument("--sobol-entry", action="store_true", help="scrambled Sobol entry positions")
     ap.add_argument("--refill-lanes", type=int, default=0, help="idle lanes before a wave refills (0 = 16)")
+    ap.add_argument("--max-walk", type=int, default=0, help="brick crossings per loop iteration (0 = automatic)")
     ap.add_argument("--brick", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched g-point measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -272,7 +273,7 @@ def main():
     def step(seed):
         raw = rt3d.trace(df, wl.sza, wl.azimuth, wl.photons, seed, brick=wl.brick, out=out, workspace=ws,
                          timed=True, lds_majorant=args.lds_majorant, merge=not args.no_merge,
-                         sobol_entry=args.sobol_entry, refill_lanes=args.refill_lanes)
+                         sobol_entry=args.sobol_entry, refill_lanes=args.refill_lanes, max_walk=args.max_walk)
         kms = rt3d.last_trace_ms()
         fin = rt3d.finalize(grid, raw, wl.photons)
         return kms, raw["stats"].clone(), fin
@@ -299,7 +300,8 @@ def main():
     bytes_per_launch = algorithmic_bytes(tot) / args.steps
     achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
     traffic = measured_traffic(wl.brick, wl.photons) \
-        if args.lds_majorant == 0 and not args.no_merge and not args.sobol_entry and args.refill_lanes == 0 else None
+        if (args.lds_majorant, args.no_merge, args.sobol_entry, args.refill_lanes, args.max_walk) == (0, False, False, 0, 0) \
+        else None
     res = {
         "metric": METRIC,
         "value": events / wall,

@@ -34,11 +34,15 @@ extern "C" {
 #endif
 
 /* Shape of one convolution: grid D x H x W, inputs c1 channels from x1 and
- * c2 (possibly 0) from x2, concatenated in that order; cout outputs. */
+ * c2 (possibly 0) from x2, concatenated in that order; cout outputs.  With
+ * up1 != 0 (ksize 3, D, H, W even) x1 is stored at half resolution
+ * [D/2][H/2][W/2][c1] and read nearest-upsampled: voxel (z, y, x) of the
+ * input is x1[z/2][y/2][x/2] (the decoder's upsampling, never written out). */
 typedef struct {
     int32_t D, H, W;
     int32_t c1, c2, cout;
     int32_t ksize; /* 1 or 3 */
+    int32_t up1;
 } rt3d_dn_conv;
 
 const char* rt3d_dn_last_error(void);
@@ -59,8 +63,8 @@ rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, 
 
 /* dw[co][t][ci] += sum_v dz[v][co] x[v + offset(t)][ci] (FP32, accumulated
  * with atomics: clear dw first); db[co] += sum_v dz[v][co] if db != NULL.
- * x = concat(x1, x2) is the forward input, dz the gradient at the
- * convolution output (after the activation's derivative). */
+ * x = concat(x1, x2) is the forward input (c->up1 must be 0), dz the
+ * gradient at the convolution output (after the activation's derivative). */
 rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
                                  float* dw, float* db, void* stream);
 

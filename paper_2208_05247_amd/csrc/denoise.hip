@@ -70,6 +70,7 @@ struct ConvArgs {
     int o1;
     float* yf;             // optional FP32 copy [vox][cout]
     int D, H, W, cout, relu;
+    int up1;               // x1 at half resolution, read nearest-upsampled
 };
 
 template <int KS>
@@ -123,6 +124,114 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const ConvArgs a) {
             if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
         } else if (a.y2) {
             a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+        }
+    }
+}
+
+// Tiled 3x3x3 convolution.  A workgroup (4 waves) owns an output tile of
+// kTY y-rows x kTX x-voxels at one z and a slab of up to 64 output channels.
+// For each 16-channel input chunk the (3 x (kTY+2) x (kTX+2))-voxel input
+// halo is staged in LDS once (zero outside the domain); every wave then runs
+// the 27 taps over its 2 rows x 2 cout tiles: A fragments are contiguous
+// 1 KiB rows of the staged halo, B fragments (weights) come from global
+// memory, where the small weight tensor stays cache resident, and each is
+// used by two MFMAs.
+constexpr int kTY = 8, kTX = 32;
+constexpr int kHaloY = kTY + 2, kHaloX = kTX + 2;
+constexpr int kHaloVox = 3 * kHaloY * kHaloX;
+
+__global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
+    __shared__ uint4 tile[kHaloVox * 2];  // 16 channels = two 16-byte halves per voxel
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, half = lane >> 5;
+    const int nslab = (a.cout + 63) / 64;
+    const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY - 1) / kTY;
+    long b = blockIdx.x;
+    const int slab = (int)(b % nslab);
+    b /= nslab;
+    const int txi = (int)(b % tiles_x);
+    b /= tiles_x;
+    const int tyi = (int)(b % tiles_y);
+    const int zz = (int)(b / tiles_y);
+    const int x0 = txi * kTX, y0 = tyi * kTY;
+    const int co0 = slab * 64;
+    const int nct = min(2, (a.cout - co0) / 32);
+    const int cin = a.c1 + a.c2;
+    const int row0 = 2 * wave;  // rows row0, row0 + 1 of the tile
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[r][ct][e] = 0.0f;
+
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+        __syncthreads();  // the previous chunk's halo is no longer read
+        for (int i = threadIdx.x; i < kHaloVox * 2; i += 256) {
+            const int v = i >> 1, part = i & 1;
+            const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY, hz = v / (kHaloX * kHaloY);
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
+                const uint16_t* src;
+                if (c0 < a.c1) {
+                    const long v1 = a.up1 ? ((long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)
+                                          : ((long)z * a.H + y) * a.W + x;
+                    src = a.x1 + v1 * a.c1 + c0;
+                } else {
+                    src = a.x2 + (((long)z * a.H + y) * a.W + x) * a.c2 + (c0 - a.c1);
+                }
+                val = *(const uint4*)(src + 8 * part);
+            }
+            tile[i] = val;
+        }
+        __syncthreads();
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            uint4 bv[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                bv[ct] = make_uint4(0u, 0u, 0u, 0u);
+                if (ct < nct) {
+                    const int co = co0 + 32 * ct + m;
+                    bv[ct] = *(const uint4*)(a.w + ((long)co * 27 + t) * cin + c0 + 8 * half);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const uint4 av = tile[((dz * kHaloY + row0 + r + dy) * kHaloX + m + dx) * 2 + half];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+                    if (ct < nct)
+                        acc[r][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[ct]),
+                                                                             acc[r][ct], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int y = y0 + row0 + r;
+        if (y >= a.H) continue;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (ct >= nct) continue;
+            const int n = co0 + 32 * ct + m;
+            const float bias = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
+                if (x >= a.W) continue;
+                float v = acc[r][ct][e] + bias;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                const long vox = ((long)zz * a.H + y) * a.W + x;
+                if (a.yf) a.yf[vox * a.cout + n] = v;
+                if (n < a.o1) {
+                    if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
+                } else if (a.y2) {
+                    a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+                }
+            }
         }
     }
 }
@@ -402,16 +511,21 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
     if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return RT3D_EINVAL;
     if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
     if (o1 <= 0 || o1 > c->cout || o1 % 32 || (o1 < c->cout && !y2)) return RT3D_EINVAL;
+    if (c->up1 && (c->ksize != 3 || c->D % 2 || c->H % 2 || c->W % 2)) return RT3D_EINVAL;
     ConvArgs a;
     a.x1 = x1; a.x2 = x2; a.c1 = c->c1; a.c2 = c->c2; a.w = w; a.bias = bias;
     a.y1 = y1; a.y2 = y2; a.o1 = o1; a.yf = yf;
     a.D = c->D; a.H = c->H; a.W = c->W; a.cout = c->cout; a.relu = relu ? 1 : 0;
-    const long waves = (long)c->D * c->H * ((c->W + 31) / 32) * (c->cout / 32);
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    if (c->ksize == 3)
-        hipLaunchKernelGGL(conv_fwd_kernel<3>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
-    else
+    a.up1 = c->up1 ? 1 : 0;
+    if (c->ksize == 3) {
+        const long tiles = (long)c->D * ((c->H + kTY - 1) / kTY) * ((c->W + kTX - 1) / kTX) * ((c->cout + 63) / 64);
+        if (tiles > 0x7fffffffL) return RT3D_EINVAL;
+        hipLaunchKernelGGL(conv3_tiled_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
+    } else {
+        const long waves = (long)c->D * c->H * ((c->W + 31) / 32) * (c->cout / 32);
+        const unsigned blocks = (unsigned)((waves + 3) / 4);
         hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
+    }
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }
@@ -428,7 +542,7 @@ rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, 
 
 rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
                                  float* dw, float* db, void* stream) {
-    if (!c || !x1 || !dz || !dw || (c->c2 > 0 && !x2)) return RT3D_EINVAL;
+    if (!c || !x1 || !dz || !dw || (c->c2 > 0 && !x2) || c->up1) return RT3D_EINVAL;
     if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return RT3D_EINVAL;
     if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
     WgradArgs a;

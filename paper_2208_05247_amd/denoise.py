@@ -39,7 +39,7 @@ LEVELS = 4
 class _Conv(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("c1", ctypes.c_int32), ("c2", ctypes.c_int32), ("cout", ctypes.c_int32),
-                ("ksize", ctypes.c_int32)]
+                ("ksize", ctypes.c_int32), ("up1", ctypes.c_int32)]
 
 
 _lib = None
@@ -102,11 +102,17 @@ def bf16_empty(*shape, device="cuda"):
 # Kernel wrappers
 # ---------------------------------------------------------------------------
 
-def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=None):
+def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=None, up1=False):
+    """One convolution; with up1, x1 is at half resolution and read
+    nearest-upsampled (the output grid is twice x1's)."""
     D, H, W, c1 = x1.shape
+    if up1:
+        D, H, W = 2 * D, 2 * H, 2 * W
     c2 = 0 if x2 is None else x2.shape[3]
+    if x2 is not None and tuple(x2.shape[:3]) != (D, H, W):
+        raise ValueError("x2 must be on the output grid")
     o1 = cout if o1 is None else o1
-    c = _Conv(D, H, W, c1, c2, cout, ksize)
+    c = _Conv(D, H, W, c1, c2, cout, ksize, 1 if up1 else 0)
     _check(load().rt3d_dn_conv3d_fwd(ctypes.byref(c), _p(x1), _p(x2), _p(w), _p(bias), int(relu), _p(y1), _p(y2),
                                      int(o1), _p(yf), _s()), "rt3d_dn_conv3d_fwd")
 
@@ -216,11 +222,13 @@ class Denoiser:
             self.bias[k].copy_(st[f"b_{k}"])
 
     # -- forward ------------------------------------------------------------
-    def _conv(self, name, x1, x2=None, yf=None):
+    def _conv(self, name, x1, x2=None, yf=None, up1=False):
         L = next(l for l in self.layers if l.name == name)
         D, H, W, _ = x1.shape
+        if up1:
+            D, H, W = 2 * D, 2 * H, 2 * W
         y = None if yf is not None else bf16_empty(D, H, W, L.cout)
-        conv_fwd(x1, x2, self.pb[name], self.bias[name], L.relu, L.cout, L.ksize, y1=y, yf=yf)
+        conv_fwd(x1, x2, self.pb[name], self.bias[name], L.relu, L.cout, L.ksize, y1=y, yf=yf, up1=up1)
         return y
 
     def forward(self, feat: torch.Tensor, keep: bool = False) -> torch.Tensor:
@@ -236,12 +244,19 @@ class Denoiser:
         a["e2"] = self._conv("e2", a["p1"])
         a["p2"] = pool2(a["e2"])
         a["b"] = self._conv("b", a["p2"])
-        a["u2"] = up2(a["b"])
-        a["d2"] = self._conv("d2", a["u2"], a["e2"])
-        a["u1"] = up2(a["d2"])
-        a["d1"] = self._conv("d1", a["u1"], a["e1"])
-        a["u0"] = up2(a["d1"])
-        a["d0"] = self._conv("d0", a["u0"], a["e0"])
+        if keep:
+            # the weight gradients read the upsampled inputs: materialise them
+            a["u2"] = up2(a["b"])
+            a["d2"] = self._conv("d2", a["u2"], a["e2"])
+            a["u1"] = up2(a["d2"])
+            a["d1"] = self._conv("d1", a["u1"], a["e1"])
+            a["u0"] = up2(a["d1"])
+            a["d0"] = self._conv("d0", a["u0"], a["e0"])
+        else:
+            # inference: the convolutions read the coarser level upsampled
+            a["d2"] = self._conv("d2", a["b"], a["e2"], up1=True)
+            a["d1"] = self._conv("d1", a["d2"], a["e1"], up1=True)
+            a["d0"] = self._conv("d0", a["d1"], a["e0"], up1=True)
         out = torch.empty(D, H, W, HEAD, dtype=torch.float32, device=feat.device)
         self._conv("head", a["d0"], yf=out)
         if keep:

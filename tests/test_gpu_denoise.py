@@ -176,3 +176,32 @@ def test_denoiser_gains_over_plain_tracing(dn):
         den = ex.eps_against(od + of, ref_a, ref_b)
         say("N", n, "eps raw", raw, "denoised", den)
         assert den < 0.7 * raw
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 10, 32, 16, 32), (2, 4, 18, 64, 32, 64), (3, 3, 5, 16, 0, 96)])
+def test_fused_upsampling_equals_materialised(dn, shape):
+    """A convolution that reads its first input nearest-upsampled on the fly
+    equals the same convolution on the materialised 2x-upsampled input, bit
+    for bit (same products, same order); partial tiles and a concatenated
+    second input included."""
+    d, h, w, c1, c2, cout = shape
+    g = torch.Generator().manual_seed(17)
+    x1 = torch.randn(d, h, w, c1, generator=g).to(torch.bfloat16).cuda()
+    x2 = torch.randn(2 * d, 2 * h, 2 * w, c2, generator=g).to(torch.bfloat16).cuda() if c2 else None
+    wt = (torch.randn(cout, 27, c1 + c2, generator=g) * 0.1).to(torch.bfloat16).cuda()
+    bias = torch.randn(cout, generator=g).cuda()
+    up = dn.up2(x1)
+    ref = torch.empty(2 * d, 2 * h, 2 * w, cout, dtype=torch.float32, device="cuda")
+    got = torch.empty_like(ref)
+    dn.conv_fwd(up, x2, wt, bias, True, cout, 3, yf=ref)
+    dn.conv_fwd(x1, x2, wt, bias, True, cout, 3, yf=got, up1=True)
+    assert torch.equal(got, ref)
+
+
+def test_inference_forward_equals_training_forward(dn):
+    net = dn.Denoiser(base=32, seed=4)
+    g = torch.Generator().manual_seed(2)
+    feat = torch.randn(16, 16, 24, 16, generator=g).to(torch.bfloat16).cuda()
+    a = net.forward(feat, keep=True)
+    b = net.forward(feat, keep=False)
+    assert torch.equal(a, b)

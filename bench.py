@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "photon events/s + time to 5% heating-rate RMS, plain vs batched+denoised"
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 
 # Algorithmic HBM bytes per event of the tracing kernel (random gathers and
 # tally read-modify-writes at the method's granularity; majorants live in
@@ -228,6 +229,42 @@ def two_stream_measurement(reps: int = 20) -> dict:
             "diffuse_fraction_range": [float(fd.min()), float(fd.max())]}
 
 
+def denoiser_measurement(reps: int = 3) -> dict:
+    """Inference time of the denoiser on the 1024x1024x128 evaluation grid
+    (random weights; time does not depend on them) and its MFMA roofline:
+    algorithmic FLOPs of the network as defined (first layer: its 4 real
+    input channels; head: its 2 real outputs) over the wall time of one
+    inference (features, every convolution, pooling, residual head)."""
+    import torch
+    from paper_2208_05247_amd import denoise as dn
+
+    D, H, W = 128, 1024, 1024
+    net = dn.Denoiser(base=32, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    hd = torch.rand(D, H, W, device="cuda", generator=g)
+    hf = torch.rand(D, H, W, device="cuda", generator=g)
+    ke = torch.rand(D, H, W, device="cuda", generator=g) * 0.01
+    flops = 0.0
+    for L in net.layers:
+        level = {"e0": 0, "e1": 1, "e2": 2, "b": 3, "d2": 2, "d1": 1, "d0": 0, "head": 0}[L.name]
+        cin = 4 if L.name == "e0" else L.c1 + L.c2
+        cout = dn.NOUT if L.name == "head" else L.cout
+        flops += 2.0 * L.ksize ** 3 * cin * cout * (D * H * W) / 8 ** level
+    dn.denoise(net, hd, hf, ke, 0.1 * ke, 20.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dn.denoise(net, hd, hf, ke, 0.1 * ke, 20.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"grid": [D, H, W], "parameters": net.n_params(), "ms_per_inference": ms,
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "flops_per_call": flops}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +277,8 @@ def main():
     ap.add_argument("--sobol-entry", action="store_true", help="scrambled Sobol entry positions")
     ap.add_argument("--refill-lanes", type=int, default=0, help="idle lanes before a wave refills (0 = 16)")
     ap.add_argument("--max-walk", type=int, default=0, help="brick crossings per loop iteration (0 = automatic)")
+    ap.add_argument("--inference-only", action="store_true",
+                    help="only time denoiser inference on the 1024x1024x128 grid (prints its JSON)")
     ap.add_argument("--brick", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched g-point measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -253,6 +292,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.calibrate_copy}), flush=True)
+        return
+    if args.inference_only:
+        print(json.dumps({"denoiser_inference": denoiser_measurement()}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tracer is single-GPU (photons or g-points would be "
@@ -334,6 +376,7 @@ def main():
         res["batched"] = batched_measurement(max(1, min(args.steps, 3)))
         res["sobol_entry"] = entry_measurement()
         res["two_stream_tod"] = two_stream_measurement()
+        res["denoiser_inference"] = denoiser_measurement()
     res["time_to_5pct_heating_rms"] = time_to_5pct()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl)

@@ -207,7 +207,7 @@ typedef struct {
                                 1 = when it fits, -1 = never */
     int32_t max_walk;        /* acceleration-grid crossings a lane makes per
                                 loop iteration before the wave re-converges;
-                                0 = automatic (unbounded with LDS majorants) */
+                                0 = automatic (3 with LDS majorants, else 2) */
     int32_t pool_photons;    /* photon ids a wave takes from the work queue
                                 at a time, 0 = 256 */
     int32_t refill_lanes;    /* a wave starts new photons once at least this

@@ -43,6 +43,8 @@ typedef struct {
     int32_t c1, c2, cout;
     int32_t ksize; /* 1 or 3 */
     int32_t up1;
+    int32_t yf_cols; /* FP32 output keeps channels [0, yf_cols) only, with
+                        row stride yf_cols; 0 = cout */
 } rt3d_dn_conv;
 
 const char* rt3d_dn_last_error(void);
@@ -50,8 +52,8 @@ const char* rt3d_dn_last_error(void);
 /* y = act(conv(concat(x1, x2), w) + bias); act = ReLU if relu != 0.
  * Output channels [0, o1) go to y1 ([vox][o1]), [o1, cout) to y2
  * ([vox][cout - o1], o1 a multiple of 32).  If yf is not NULL the FP32
- * values are also written to yf [vox][cout] (y1 may then be NULL when
- * o1 == cout).  bias may be NULL.  With flipped weights (rt3d_dn_flip_weights)
+ * values of channels [0, yf_cols) are also written to yf [vox][yf_cols] (y1
+ * may then be NULL when o1 == cout).  bias may be NULL.  With flipped weights (rt3d_dn_flip_weights)
  * and no bias/activation this computes the data gradient. */
 rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* w,
                                const float* bias, int32_t relu, uint16_t* y1, uint16_t* y2, int32_t o1, float* yf,

@@ -68,9 +68,10 @@ struct ConvArgs {
     uint16_t* y1;          // channels [0, o1)
     uint16_t* y2;          // channels [o1, cout)
     int o1;
-    float* yf;             // optional FP32 copy [vox][cout]
+    float* yf;             // optional FP32 copy [vox][yf_cols] of channels < yf_cols
     int D, H, W, cout, relu;
     int up1;               // x1 at half resolution, read nearest-upsampled
+    int yf_cols;
 };
 
 template <int KS>
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const ConvArgs a) {
         float v = acc[r] + b;
         if (a.relu) v = fmaxf(v, 0.0f);
         const long vox = ((long)zz * a.H + yy) * a.W + x;
-        if (a.yf) a.yf[vox * a.cout + n] = v;
+        if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
         if (n < a.o1) {
             if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
         } else if (a.y2) {
@@ -225,12 +226,108 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
                 float v = acc[r][ct][e] + bias;
                 if (a.relu) v = fmaxf(v, 0.0f);
                 const long vox = ((long)zz * a.H + y) * a.W + x;
-                if (a.yf) a.yf[vox * a.cout + n] = v;
+                if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
                 if (n < a.o1) {
                     if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
                 } else if (a.y2) {
                     a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
                 }
+            }
+        }
+    }
+}
+
+// 3x3x3 convolution with exactly 32 output channels (one MFMA column tile,
+// so an input fragment cannot be shared between output-channel tiles).
+// Instead each wave owns 4 output rows and, per z-slice of the kernel, keeps
+// its 9 weight fragments of the current 16-channel chunk in registers: it
+// walks the 6 staged input rows its outputs need, 3 x-shifts each, and feeds
+// every fragment it reads from LDS to all (up to 3) of its output rows that
+// use it.  Workgroup tile:
+// 16 rows x 32 voxels at one z.
+constexpr int kTY32 = 16;
+constexpr int kHaloY32 = kTY32 + 2;
+constexpr int kHaloVox32 = 3 * kHaloY32 * kHaloX;
+
+__global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
+    __shared__ uint4 tile[kHaloVox32 * 2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, half = lane >> 5;
+    const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY32 - 1) / kTY32;
+    long b = blockIdx.x;
+    const int txi = (int)(b % tiles_x);
+    b /= tiles_x;
+    const int tyi = (int)(b % tiles_y);
+    const int zz = (int)(b / tiles_y);
+    const int x0 = txi * kTX, y0 = tyi * kTY32;
+    const int cin = a.c1 + a.c2;
+    const int row0 = 4 * wave;
+    f32x16 acc[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[o][e] = 0.0f;
+
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kHaloVox32 * 2; i += 256) {
+            const int v = i >> 1, part = i & 1;
+            const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
+                const uint16_t* src;
+                if (c0 < a.c1) {
+                    const long v1 = a.up1 ? ((long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)
+                                          : ((long)z * a.H + y) * a.W + x;
+                    src = a.x1 + v1 * a.c1 + c0;
+                } else {
+                    src = a.x2 + (((long)z * a.H + y) * a.W + x) * a.c2 + (c0 - a.c1);
+                }
+                val = *(const uint4*)(src + 8 * part);
+            }
+            tile[i] = val;
+        }
+        __syncthreads();
+        for (int dz = 0; dz < 3; ++dz) {
+            // the 9 weight fragments of this z-slice of the kernel
+            uint4 bv[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                bv[t] = *(const uint4*)(a.w + ((long)m * 27 + dz * 9 + t) * cin + c0 + 8 * half);
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const uint4 av = tile[((dz * kHaloY32 + row0 + r) * kHaloX + m + dx) * 2 + half];
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        const int dy = r - o;  // output row o reads halo row o + dy
+                        if (dy >= 0 && dy <= 2)
+                            acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[dy * 3 + dx]),
+                                                                             acc[o], 0, 0, 0);
+                    }
+                }
+        }
+    }
+    const int n = m;
+    const float bias = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int y = y0 + row0 + o;
+        if (y >= a.H) continue;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
+            if (x >= a.W) continue;
+            float v = acc[o][e] + bias;
+            if (a.relu) v = fmaxf(v, 0.0f);
+            const long vox = ((long)zz * a.H + y) * a.W + x;
+            if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
+            if (n < a.o1) {
+                if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
+            } else if (a.y2) {
+                a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
             }
         }
     }
@@ -512,12 +609,18 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
     if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
     if (o1 <= 0 || o1 > c->cout || o1 % 32 || (o1 < c->cout && !y2)) return RT3D_EINVAL;
     if (c->up1 && (c->ksize != 3 || c->D % 2 || c->H % 2 || c->W % 2)) return RT3D_EINVAL;
+    if (c->yf_cols < 0 || c->yf_cols > c->cout) return RT3D_EINVAL;
     ConvArgs a;
     a.x1 = x1; a.x2 = x2; a.c1 = c->c1; a.c2 = c->c2; a.w = w; a.bias = bias;
     a.y1 = y1; a.y2 = y2; a.o1 = o1; a.yf = yf;
     a.D = c->D; a.H = c->H; a.W = c->W; a.cout = c->cout; a.relu = relu ? 1 : 0;
     a.up1 = c->up1 ? 1 : 0;
-    if (c->ksize == 3) {
+    a.yf_cols = c->yf_cols ? c->yf_cols : c->cout;
+    if (c->ksize == 3 && c->cout == 32) {
+        const long tiles = (long)c->D * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
+        if (tiles > 0x7fffffffL) return RT3D_EINVAL;
+        hipLaunchKernelGGL(conv3_c32_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
+    } else if (c->ksize == 3) {
         const long tiles = (long)c->D * ((c->H + kTY - 1) / kTY) * ((c->W + kTX - 1) / kTX) * ((c->cout + 63) / 64);
         if (tiles > 0x7fffffffL) return RT3D_EINVAL;
         hipLaunchKernelGGL(conv3_tiled_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);

@@ -1074,7 +1074,7 @@ rt3d_status launch_trace(Launch& L, bool factored, hipStream_t st) {
     const size_t lds = use_lds ? maj_bytes : 0;
     // crossings per loop iteration: unbounded with majorants in LDS; with
     // majorants read through L2 a short walk keeps the lanes in step
-    L.P.max_walk = L.o.max_walk > 0 ? L.o.max_walk : (use_lds ? 0x7fffffff : 2);
+    L.P.max_walk = L.o.max_walk > 0 ? L.o.max_walk : (use_lds ? 3 : 2);
     auto kernel = factored ? (use_lds ? trace_kernel<true, true> : trace_kernel<false, true>)
                            : (use_lds ? trace_kernel<true, false> : trace_kernel<false, false>);
     int ncu = 0;

@@ -39,7 +39,7 @@ LEVELS = 4
 class _Conv(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("c1", ctypes.c_int32), ("c2", ctypes.c_int32), ("cout", ctypes.c_int32),
-                ("ksize", ctypes.c_int32), ("up1", ctypes.c_int32)]
+                ("ksize", ctypes.c_int32), ("up1", ctypes.c_int32), ("yf_cols", ctypes.c_int32)]
 
 
 _lib = None
@@ -102,9 +102,10 @@ def bf16_empty(*shape, device="cuda"):
 # Kernel wrappers
 # ---------------------------------------------------------------------------
 
-def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=None, up1=False):
+def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=None, up1=False, yf_cols=0):
     """One convolution; with up1, x1 is at half resolution and read
-    nearest-upsampled (the output grid is twice x1's)."""
+    nearest-upsampled (the output grid is twice x1's); yf (FP32) keeps the
+    first yf_cols channels (0: all)."""
     D, H, W, c1 = x1.shape
     if up1:
         D, H, W = 2 * D, 2 * H, 2 * W
@@ -112,7 +113,9 @@ def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=N
     if x2 is not None and tuple(x2.shape[:3]) != (D, H, W):
         raise ValueError("x2 must be on the output grid")
     o1 = cout if o1 is None else o1
-    c = _Conv(D, H, W, c1, c2, cout, ksize, 1 if up1 else 0)
+    if yf is not None and yf.shape[-1] != (yf_cols or cout):
+        raise ValueError("yf must have yf_cols channels")
+    c = _Conv(D, H, W, c1, c2, cout, ksize, 1 if up1 else 0, int(yf_cols))
     _check(load().rt3d_dn_conv3d_fwd(ctypes.byref(c), _p(x1), _p(x2), _p(w), _p(bias), int(relu), _p(y1), _p(y2),
                                      int(o1), _p(yf), _s()), "rt3d_dn_conv3d_fwd")
 
@@ -222,17 +225,19 @@ class Denoiser:
             self.bias[k].copy_(st[f"b_{k}"])
 
     # -- forward ------------------------------------------------------------
-    def _conv(self, name, x1, x2=None, yf=None, up1=False):
+    def _conv(self, name, x1, x2=None, yf=None, up1=False, yf_cols=0):
         L = next(l for l in self.layers if l.name == name)
         D, H, W, _ = x1.shape
         if up1:
             D, H, W = 2 * D, 2 * H, 2 * W
         y = None if yf is not None else bf16_empty(D, H, W, L.cout)
-        conv_fwd(x1, x2, self.pb[name], self.bias[name], L.relu, L.cout, L.ksize, y1=y, yf=yf, up1=up1)
+        conv_fwd(x1, x2, self.pb[name], self.bias[name], L.relu, L.cout, L.ksize, y1=y, yf=yf, up1=up1,
+                 yf_cols=yf_cols)
         return y
 
     def forward(self, feat: torch.Tensor, keep: bool = False) -> torch.Tensor:
-        """feat: BF16 [D][H][W][16]; returns FP32 head output [D][H][W][32]."""
+        """feat: BF16 [D][H][W][16]; returns the FP32 head output [D][H][W][32]
+        with keep (training) or its NOUT used channels [D][H][W][2]."""
         D, H, W, _ = feat.shape
         if D % 8 or H % 8 or W % 8:
             raise ValueError("grid dimensions must be multiples of 8 (three pooling levels)")
@@ -257,8 +262,11 @@ class Denoiser:
             a["d2"] = self._conv("d2", a["b"], a["e2"], up1=True)
             a["d1"] = self._conv("d1", a["d2"], a["e1"], up1=True)
             a["d0"] = self._conv("d0", a["d1"], a["e0"], up1=True)
-        out = torch.empty(D, H, W, HEAD, dtype=torch.float32, device=feat.device)
-        self._conv("head", a["d0"], yf=out)
+        # training needs every head channel (its gradient); inference only
+        # the NOUT used ones
+        nkeep = HEAD if keep else NOUT
+        out = torch.empty(D, H, W, nkeep, dtype=torch.float32, device=feat.device)
+        self._conv("head", a["d0"], yf=out, yf_cols=nkeep)
         if keep:
             self.acts = a
         return out
@@ -358,7 +366,8 @@ def mse(out: torch.Tensor, base: torch.Tensor, target: Optional[torch.Tensor], w
     pred = torch.empty_like(base)
     dout = bf16_empty(*out.shape) if want_grad else None
     loss = torch.zeros(1, dtype=torch.float64, device=out.device) if target is not None else None
-    _check(load().rt3d_dn_mse(_p(out), HEAD, _p(base), _p(target), NOUT, nvox, _p(pred), _p(dout), _p(loss), _s()),
+    _check(load().rt3d_dn_mse(_p(out), out.shape[-1], _p(base), _p(target), NOUT, nvox, _p(pred), _p(dout),
+                              _p(loss), _s()),
            "rt3d_dn_mse")
     return pred, dout, (None if loss is None else loss / (nvox * NOUT))
 

@@ -124,7 +124,7 @@ def scene(seed: int, nx: int, ny: int, nz: int, dx: float, dz: float, sza=None, 
 
 
 def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: int, dx: float, dz: float,
-          low=(64, 128, 256, 512, 1024), high: int = 8192, lr: float = 1e-3, seed0: int = 0):
+          low=(64, 128, 192, 256, 384, 512, 1024), high: int = 8192, lr: float = 1e-3, seed0: int = 0):
     """Train on tracer-generated pairs: one new random scene per field,
     `steps_per_field` noisy realisations against one high-photon target."""
     losses = []
@@ -157,7 +157,8 @@ def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: in
     return losses, t_steps / max(step, 1)
 
 
-def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024), low=(64, 128, 256, 512, 1024)):
+def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
+             low=(64, 128, 192, 256, 320, 384, 512, 768, 1024)):
     tr = Tracer(wl)
     g = tr.grid
     log("reference halves ...")
@@ -223,7 +224,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="small grids and few fields (smoke run)")
     ap.add_argument("--out", default=None)
-    ap.add_argument("--train-fields", type=int, default=200)
+    ap.add_argument("--train-fields", type=int, default=400)
     ap.add_argument("--steps-per-field", type=int, default=8)
     args = ap.parse_args()
     torch.manual_seed(0)

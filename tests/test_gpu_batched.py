@@ -209,3 +209,74 @@ def test_more_than_2_31_photons_in_one_launch(rt3d):
     assert np.all(np.abs(counts - n / 16) <= 1e-5 * n / 16)
     with pytest.raises(rt3d.Rt3dError):
         rt3d.trace(df, 0.0, 0.0, 1 << 33, 17, brick=(4, 4, 1))
+
+
+def direct_expectation(m, sza, azimuth, counts, cols):
+    """Expected broadband direct surface irradiance (fraction of the TOD
+    flux) of sampled columns for photon counts `counts` per g-point.  Every
+    g-point's gas is horizontally uniform, so along the straight slant path
+    of an unscattered photon its optical depth is its column optical depth
+    over mu0, exactly; the per-g-point transmittance is that factor times
+    the cloud field's, which the oracle gives as deterministic line
+    integrals over a lattice of entry points."""
+    grid = m.grid
+    kc = np.ascontiguousarray(m.k_cloud, dtype=np.float32)
+    zeros = np.zeros_like(kc)
+    cloud = syn.Fields(grid, kc, kc, zeros, zeros, np.zeros(grid.shape2, dtype=np.float32))
+    tc = oracle.direct_transmittance(cloud, sza, azimuth, cols, n=16)
+    mu0 = np.cos(np.radians(sza))
+    tau_gas = m.k_gas.astype(np.float64).sum(axis=1) * grid.dz
+    share = np.asarray(counts, dtype=np.float64) / float(np.sum(counts))
+    return tc * float(np.sum(share * np.exp(-tau_gas / mu0)))
+
+
+def check_direct_columns(rt3d, m, raw, total, sza, azimuth, n_cols=48, seed=0):
+    grid = m.grid
+    per_col = total / (grid.nx * grid.ny)
+    h = rt3d.to_host(raw)
+    sfc = h["sfc_dir"].astype(np.float64) / (per_col * W1)
+    rng = np.random.default_rng(seed)
+    cols = [(int(i), int(j)) for i, j in zip(rng.integers(0, grid.nx, n_cols), rng.integers(0, grid.ny, n_cols))]
+    return h, cols, sfc, per_col
+
+
+def test_batched_full_size_direct_irradiance(rt3d):
+    """The batched 512x512x96 workload at its full 2^28 photons in the
+    benchmark's launch configuration: direct irradiance of 48 sampled
+    columns against the factorised expectation (5 SE), exact ledger."""
+    wl = syn.batched_cumulus()
+    m = wl.medium
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    total = int(wl.photons.sum())
+    raw = rt3d.trace_batched(dm, wl.sza, wl.azimuth, wl.photons, 11, brick=wl.brick)
+    h, cols, sfc, per_col = check_direct_columns(rt3d, m, raw, total, wl.sza, wl.azimuth)
+    ledger_ok(h, total)
+    ref = direct_expectation(m, wl.sza, wl.azimuth, wl.photons, cols)
+    got = np.array([sfc[j, i] for i, j in cols])
+    se = np.sqrt(np.maximum(ref * (1 - ref), 1e-4) / per_col)
+    say("batched direct columns: max |z|", float(np.max(np.abs(got - ref) / se)))
+    assert np.all(np.abs(got - ref) <= 5 * se + 1e-3), np.c_[got, ref, se]
+
+
+def test_large_combined_full_size(rt3d):
+    """The large combined workload: 1024x1024x128 cells of 25x25x20 m, 112
+    g-points, 2^30 photons in one launch, SZA 60 (strong side illumination),
+    albedo U[0.1, 0.3] per column.  Exact ledger, photons per g-point as
+    asked, and the direct irradiance of 48 sampled columns against the
+    factorised expectation."""
+    from paper_2208_05247_amd import experiment as ex
+    wl = ex.scene(99_999, 1024, 1024, 128, 25.0, 20.0, sza=60.0, az=0.0, photons=1 << 30)
+    m = wl.medium
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    total = int(wl.photons.sum())
+    assert total == 1 << 30
+    raw = rt3d.trace_batched(dm, wl.sza, wl.azimuth, wl.photons, 21, brick=wl.brick, timed=True)
+    ms = rt3d.last_trace_ms()
+    h, cols, sfc, per_col = check_direct_columns(rt3d, m, raw, total, wl.sza, wl.azimuth, seed=3)
+    ledger_ok(h, total)
+    say("large combined: kernel ms", ms, "photons/s", total / ms * 1e3)
+    ref = direct_expectation(m, wl.sza, wl.azimuth, wl.photons, cols)
+    got = np.array([sfc[j, i] for i, j in cols])
+    se = np.sqrt(np.maximum(ref * (1 - ref), 1e-4) / per_col)
+    say("large direct columns: max |z|", float(np.max(np.abs(got - ref) / se)))
+    assert np.all(np.abs(got - ref) <= 5 * se + 1e-3), np.c_[got, ref, se]

@@ -220,13 +220,58 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
     return res
 
 
+def config3(out_path=None, n_train: int = 200, n_heldout: int = 20, steps_per_field: int = 8):
+    """The denoiser configuration taken literally: fields of 256x256x96
+    cells of 50x50x32 m, 112 g-points, trained on 200 seeded fields with
+    inputs at 4 photons per column and targets at 1024, then evaluated on 20
+    held-out fields (seeds 200-219): heating-rate error eps of the raw and
+    the denoised 4-photon fields against a reference of two independent
+    1024-photon halves (its own noise removed)."""
+    torch.manual_seed(0)
+    nx, nz, dx, dz = 256, 96, 50.0, 32.0
+    net = dn.Denoiser(base=32, seed=0)
+    t0 = time.perf_counter()
+    losses, step_s = train(net, n_train, steps_per_field, nx, nz, dx, dz, low=(4,), high=1024)
+    train_s = time.perf_counter() - t0
+    rows = []
+    for k in range(n_heldout):
+        wl = scene(n_train + k, nx, nx, nz, dx, dz)
+        tr = Tracer(wl)
+        a_dir, a_dif, _, _ = tr.heating(1024, seed=800_000_000 + 10 * k)
+        b_dir, b_dif, _, _ = tr.heating(1024, seed=800_000_001 + 10 * k)
+        ref_a, ref_b = (a_dir + a_dif).clone(), (b_dir + b_dif).clone()
+        hd, hf, _, _ = tr.heating(4, seed=900_000_000 + 10 * k)
+        kext, kabs = tr.k_mean()
+        od, of = dn.denoise(net, hd, hf, kext, kabs, dz)
+        rows.append({"seed": n_train + k, "sza": wl.sza, "eps_raw": eps_against(hd + hf, ref_a, ref_b),
+                     "eps_denoised": eps_against(od + of, ref_a, ref_b)})
+        log(f"held-out field {k}: sza {wl.sza:.1f} eps raw {rows[-1]['eps_raw']:.3f} -> "
+            f"{rows[-1]['eps_denoised']:.3f}")
+        del tr
+    res = {"grid": [nx, nx, nz], "cell_m": [dx, dx, dz], "g_points": 112, "train_fields": n_train,
+           "train_steps": len(losses), "train_seconds": train_s, "ms_per_train_step": 1e3 * step_s,
+           "input_photons_per_column": 4, "target_photons_per_column": 1024, "heldout": rows,
+           "mean_eps_raw": float(np.mean([r["eps_raw"] for r in rows])),
+           "mean_eps_denoised": float(np.mean([r["eps_denoised"] for r in rows]))}
+    log(json.dumps({k: v for k, v in res.items() if k != "heldout"}))
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(res, f, indent=1)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="small grids and few fields (smoke run)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--train-fields", type=int, default=400)
     ap.add_argument("--steps-per-field", type=int, default=8)
+    ap.add_argument("--config3", action="store_true",
+                    help="train/evaluate on 256x256x96 fields (4-photon inputs, 1024-photon targets) instead")
     args = ap.parse_args()
+    if args.config3:
+        config3(args.out)
+        return
     torch.manual_seed(0)
     if args.quick:
         tr_nx, ev_nx, nz, dx, dz, nf, ref = 64, 128, 64, 25.0, 20.0, 6, 4096

@@ -6,7 +6,7 @@
  * in N_sample.  This library adds a small 3D convolutional encoder-decoder
  * that maps low-photon heating tallies (plus the extinction field) to
  * high-photon ones; it is trained on tally pairs produced by the tracer
- * itself, and plain high-photon tracing remains the reference that judges
+ * itself, and plain high-photon tracing remains the reference that measures
  * its error.  Not part of the paper's method.
  *
  * Conventions (all pointers are DEVICE pointers owned by the caller; every

@@ -158,7 +158,7 @@ def test_denoiser_gains_over_plain_tracing(dn):
     """Trained briefly on tracer-generated pairs (24 random cumulus scenes,
     64x64x64 cells of 25x25x20 m, 112 g-points), the network lowers the
     heating-rate RMS error of a held-out scene at equal photon counts; plain
-    high-photon tracing (two independent halves) is the judge."""
+    high-photon tracing (two independent halves) is the reference."""
     from paper_2208_05247_amd import experiment as ex
     net = dn.Denoiser(base=32, seed=0)
     losses, _ = ex.train(net, 24, 4, 64, 64, 25.0, 20.0, high=4096)

@@ -281,7 +281,7 @@ def main():
     log(f"denoiser parameters: {net.n_params()}")
     t0 = time.perf_counter()
     losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz,
-                           high=2048 if args.quick else 8192)
+                           high=2048 if args.quick else 16384)
     train_s = time.perf_counter() - t0
     wl = scene(99_999, ev_nx, ev_nx, nz, dx, dz, sza=60.0, az=0.0, photons=1 << 30)
     res = evaluate(net, wl, ref)

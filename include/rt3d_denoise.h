@@ -25,6 +25,7 @@
 #ifndef RT3D_DENOISE_H
 #define RT3D_DENOISE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "rt3d.h"
@@ -69,6 +70,20 @@ rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, 
  * gradient at the convolution output (after the activation's derivative). */
 rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
                                  float* dw, float* db, void* stream);
+
+/* Bytes of workspace rt3d_dn_conv3d_wgrad_ws needs for this shape (0 on bad
+ * arguments).  Host call. */
+size_t rt3d_dn_wgrad_workspace_size(const rt3d_dn_conv* c);
+
+/* rt3d_dn_conv3d_wgrad with a caller-owned DEVICE workspace (at least
+ * rt3d_dn_wgrad_workspace_size bytes, 256-byte aligned, contents need not be
+ * initialised): every row chunk of the reduction stores its partial dw (and
+ * every block its partial db) there, and the partials are added to dw / db
+ * in a fixed order, so the result does not depend on scheduling (bitwise
+ * reproducible; the plain variant adds with FP32 atomics). */
+rt3d_status rt3d_dn_conv3d_wgrad_ws(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2,
+                                    const uint16_t* dz, float* dw, float* db, void* workspace,
+                                    size_t workspace_bytes, void* stream);
 
 /* dz = dy where y > 0 else 0 (ReLU derivative through its output y). */
 rt3d_status rt3d_dn_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dz, uint64_t n, void* stream);

@@ -358,6 +358,7 @@ struct WgradArgs {
     const uint16_t* x2;
     int c1, c2;
     float* dw;
+    float* partial;  // per-row-chunk partial dw [chunks][cout][taps][cin], or null: atomics into dw
     int D, H, W, rows_per_wave;
 };
 
@@ -415,13 +416,18 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(const WgradArgs a) {
     if (n < cin) {
         for (int r = 0; r < 16; ++r) {
             const int mm = cot * 32 + 8 * (r >> 2) + 4 * half + (r & 3);  // output channel (row)
-            atomicAdd(&a.dw[((long)mm * taps + t) * cin + n], acc[r]);
+            if (a.partial)
+                a.partial[((chunk * a.cout + mm) * taps + t) * cin + n] = acc[r];
+            else
+                atomicAdd(&a.dw[((long)mm * taps + t) * cin + n], acc[r]);
         }
     }
 }
 
-// db[c] += sum over voxels of dz[v][c]
-__global__ void bias_grad_kernel(const uint16_t* __restrict__ dz, float* __restrict__ db, size_t nvox, int c) {
+// db[c] += sum over voxels of dz[v][c]; with `partial`, block b stores its
+// sum in partial[b][c] instead (summed in a fixed order afterwards)
+__global__ void bias_grad_kernel(const uint16_t* __restrict__ dz, float* __restrict__ db, size_t nvox, int c,
+                                 float* __restrict__ partial) {
     __shared__ float part[256];
     const int ch = blockIdx.y;
     float s = 0.0f;
@@ -433,7 +439,20 @@ __global__ void bias_grad_kernel(const uint16_t* __restrict__ dz, float* __restr
         if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(&db[ch], part[0]);
+    if (threadIdx.x == 0) {
+        if (partial) partial[(size_t)blockIdx.x * c + ch] = part[0];
+        else atomicAdd(&db[ch], part[0]);
+    }
+}
+
+// out[i] += sum over p = 0 .. nparts-1, in that order, of partial[p][i]
+__global__ void sum_partials_kernel(const float* __restrict__ partial, float* __restrict__ out, size_t n,
+                                    int nparts) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * n + i];
+        out[i] += s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -643,37 +662,100 @@ rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, 
     return RT3D_OK;
 }
 
-rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
-                                 float* dw, float* db, void* stream) {
-    if (!c || !x1 || !dz || !dw || (c->c2 > 0 && !x2) || c->up1) return RT3D_EINVAL;
-    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return RT3D_EINVAL;
-    if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Launch plan of the weight gradient: the (output tile, input tile, tap)
+// tasks are split over row chunks so that about 4096 waves are in flight.
+struct WgradPlan {
     WgradArgs a;
-    a.dz = dz; a.cout = c->cout; a.x1 = x1; a.x2 = x2; a.c1 = c->c1; a.c2 = c->c2; a.dw = dw;
+    long chunks, waves;
+    int taps;
+    size_t nw;            // cout * taps * cin
+    unsigned bias_blocks; // blocks per channel of the bias gradient
+    size_t ws_bytes;      // workspace of the deterministic variant
+};
+
+bool wgrad_plan(const rt3d_dn_conv* c, WgradPlan* p) {
+    if (!c || c->up1) return false;
+    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return false;
+    if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return false;
+    WgradArgs& a = p->a;
+    a.cout = c->cout; a.c1 = c->c1; a.c2 = c->c2;
     a.D = c->D; a.H = c->H; a.W = c->W;
-    const int taps = c->ksize * c->ksize * c->ksize;
-    const long base_tasks = (long)(c->cout / 32) * ((c->c1 + c->c2 + 31) / 32) * taps;
+    a.partial = nullptr;
+    p->taps = c->ksize * c->ksize * c->ksize;
+    const long base_tasks = (long)(c->cout / 32) * ((c->c1 + c->c2 + 31) / 32) * p->taps;
     const long nrows = (long)c->D * c->H;
-    // about 4096 waves in flight, at least one row each
     long chunks = 4096 / base_tasks;
     if (chunks < 1) chunks = 1;
     if (chunks > nrows) chunks = nrows;
     a.rows_per_wave = (int)((nrows + chunks - 1) / chunks);
-    const long waves = base_tasks * ((nrows + a.rows_per_wave - 1) / a.rows_per_wave);
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    hipStream_t st = (hipStream_t)stream;
+    p->chunks = (nrows + a.rows_per_wave - 1) / a.rows_per_wave;
+    p->waves = base_tasks * p->chunks;
+    p->nw = (size_t)c->cout * p->taps * (c->c1 + c->c2);
+    const size_t nvox = (size_t)c->D * c->H * c->W;
+    p->bias_blocks = blocks_for(nvox, 256, 256);
+    p->ws_bytes = ((p->chunks * p->nw * sizeof(float) + 255) / 256) * 256 +
+                  (size_t)p->bias_blocks * c->cout * sizeof(float);
+    return true;
+}
+
+rt3d_status wgrad_run(const rt3d_dn_conv* c, const WgradPlan& plan, const uint16_t* x1, const uint16_t* x2,
+                      const uint16_t* dz, float* dw, float* db, float* part_w, float* part_b, hipStream_t st) {
+    WgradArgs a = plan.a;
+    a.dz = dz; a.x1 = x1; a.x2 = x2; a.dw = dw; a.partial = part_w;
+    const unsigned blocks = (unsigned)((plan.waves + 3) / 4);
     if (c->ksize == 3)
         hipLaunchKernelGGL(conv_wgrad_kernel<3>, dim3(blocks), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(conv_wgrad_kernel<1>, dim3(blocks), dim3(256), 0, st, a);
     DN_TRY(hipGetLastError());
-    if (db) {
-        const size_t nvox = (size_t)c->D * c->H * c->W;
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(nvox, 256, 256), c->cout), dim3(256), 0, st, dz, db,
-                           nvox, c->cout);
+    if (part_w) {
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks_for(plan.nw)), dim3(256), 0, st, part_w, dw, plan.nw,
+                           (int)plan.chunks);
         DN_TRY(hipGetLastError());
     }
+    if (db) {
+        const size_t nvox = (size_t)c->D * c->H * c->W;
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(plan.bias_blocks, c->cout), dim3(256), 0, st, dz, db, nvox,
+                           c->cout, part_b);
+        DN_TRY(hipGetLastError());
+        if (part_b) {
+            hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, part_b, db, (size_t)c->cout,
+                               (int)plan.bias_blocks);
+            DN_TRY(hipGetLastError());
+        }
+    }
     return RT3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt3d_status rt3d_dn_conv3d_wgrad(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* dz,
+                                 float* dw, float* db, void* stream) {
+    WgradPlan plan;
+    if (!x1 || !dz || !dw || (c && c->c2 > 0 && !x2) || !wgrad_plan(c, &plan)) return RT3D_EINVAL;
+    return wgrad_run(c, plan, x1, x2, dz, dw, db, nullptr, nullptr, (hipStream_t)stream);
+}
+
+size_t rt3d_dn_wgrad_workspace_size(const rt3d_dn_conv* c) {
+    WgradPlan plan;
+    return wgrad_plan(c, &plan) ? plan.ws_bytes : 0;
+}
+
+rt3d_status rt3d_dn_conv3d_wgrad_ws(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2,
+                                    const uint16_t* dz, float* dw, float* db, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
+    WgradPlan plan;
+    if (!x1 || !dz || !dw || (c && c->c2 > 0 && !x2) || !wgrad_plan(c, &plan)) return RT3D_EINVAL;
+    if (!workspace || workspace_bytes < plan.ws_bytes || ((uintptr_t)workspace & 255)) return RT3D_EINVAL;
+    float* part_w = (float*)workspace;
+    float* part_b = (float*)((char*)workspace + ((plan.chunks * plan.nw * sizeof(float) + 255) / 256) * 256);
+    return wgrad_run(c, plan, x1, x2, dz, dw, db, part_w, part_b, (hipStream_t)stream);
 }
 
 rt3d_status rt3d_dn_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dz, uint64_t n, void* stream) {

@@ -1072,8 +1072,8 @@ rt3d_status launch_trace(Launch& L, bool factored, hipStream_t st) {
     const bool use_lds =
         L.ngp == 1 && L.o.lds_majorant >= 0 && maj_bytes <= lds_limit && maj_bytes + 1024 <= (size_t)max_lds;
     const size_t lds = use_lds ? maj_bytes : 0;
-    // crossings per loop iteration: unbounded with majorants in LDS; with
-    // majorants read through L2 a short walk keeps the lanes in step
+    // crossings per loop iteration: a short walk keeps the lanes of a wave
+    // in step (a long clear-sky walk of one lane would hold the others)
     L.P.max_walk = L.o.max_walk > 0 ? L.o.max_walk : (use_lds ? 3 : 2);
     auto kernel = factored ? (use_lds ? trace_kernel<true, true> : trace_kernel<false, true>)
                            : (use_lds ? trace_kernel<true, false> : trace_kernel<false, false>);

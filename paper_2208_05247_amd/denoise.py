@@ -55,6 +55,7 @@ def load():
         "rt3d_dn_conv3d_fwd": [ctypes.POINTER(_Conv), P, P, P, P, I, P, P, I, P, P],
         "rt3d_dn_flip_weights": [P, P, I, I, I, P],
         "rt3d_dn_conv3d_wgrad": [ctypes.POINTER(_Conv), P, P, P, P, P, P],
+        "rt3d_dn_conv3d_wgrad_ws": [ctypes.POINTER(_Conv), P, P, P, P, P, P, ctypes.c_size_t, P],
         "rt3d_dn_relu_bwd": [P, P, P, U, P],
         "rt3d_dn_add": [P, P, P, U, P],
         "rt3d_dn_pool2": [P, P, I, I, I, I, I, P],
@@ -70,11 +71,14 @@ def load():
         f.argtypes = args
         f.restype = ctypes.c_int
     lib.rt3d_dn_last_error.restype = ctypes.c_char_p
+    lib.rt3d_dn_wgrad_workspace_size.argtypes = [ctypes.POINTER(_Conv)]
+    lib.rt3d_dn_wgrad_workspace_size.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
 
 EXPORTS = ("rt3d_dn_last_error", "rt3d_dn_conv3d_fwd", "rt3d_dn_flip_weights", "rt3d_dn_conv3d_wgrad",
+           "rt3d_dn_conv3d_wgrad_ws", "rt3d_dn_wgrad_workspace_size",
            "rt3d_dn_relu_bwd", "rt3d_dn_add", "rt3d_dn_pool2", "rt3d_dn_up2", "rt3d_dn_mse", "rt3d_dn_adam",
            "rt3d_dn_to_bf16", "rt3d_dn_features", "rt3d_dn_unfeature")
 
@@ -124,12 +128,27 @@ def flip(w, cout, cin, ksize, out):
     _check(load().rt3d_dn_flip_weights(_p(w), _p(out), cout, cin, ksize, _s()), "rt3d_dn_flip_weights")
 
 
-def conv_wgrad(x1, x2, dz, cout, ksize, dw, db):
+def wgrad_workspace_size(x1, x2, cout, ksize) -> int:
+    D, H, W, c1 = x1.shape
+    c2 = 0 if x2 is None else x2.shape[3]
+    return int(load().rt3d_dn_wgrad_workspace_size(ctypes.byref(_Conv(D, H, W, c1, c2, cout, ksize))))
+
+
+def conv_wgrad(x1, x2, dz, cout, ksize, dw, db, workspace=None):
+    """Weight (and bias) gradient, added to dw (db).  With a workspace
+    (uint8 device tensor of at least wgrad_workspace_size bytes) the sums run
+    in a fixed order and the result is bitwise reproducible; without one,
+    FP32 atomics."""
     D, H, W, c1 = x1.shape
     c2 = 0 if x2 is None else x2.shape[3]
     c = _Conv(D, H, W, c1, c2, cout, ksize)
-    _check(load().rt3d_dn_conv3d_wgrad(ctypes.byref(c), _p(x1), _p(x2), _p(dz), _p(dw), _p(db), _s()),
-           "rt3d_dn_conv3d_wgrad")
+    if workspace is None:
+        _check(load().rt3d_dn_conv3d_wgrad(ctypes.byref(c), _p(x1), _p(x2), _p(dz), _p(dw), _p(db), _s()),
+               "rt3d_dn_conv3d_wgrad")
+    else:
+        _check(load().rt3d_dn_conv3d_wgrad_ws(ctypes.byref(c), _p(x1), _p(x2), _p(dz), _p(dw), _p(db),
+                                              _p(workspace), workspace.numel() * workspace.element_size(), _s()),
+               "rt3d_dn_conv3d_wgrad_ws")
 
 
 def relu_bwd(dy, y, out):
@@ -211,6 +230,7 @@ class Denoiser:
             self.mb1[L.name] = torch.zeros_like(self.bias[L.name])
             self.mb2[L.name] = torch.zeros_like(self.bias[L.name])
         self.step_count = 0
+        self.wg_ws = None
 
     def n_params(self) -> int:
         return sum(v.numel() for v in self.p.values()) + sum(v.numel() for v in self.bias.values())
@@ -280,8 +300,13 @@ class Denoiser:
         conv_fwd(dz, None, wt, None, False, cin, L.ksize, y1=out1, y2=out2, o1=L.c1)
 
     def _wgrad(self, name, x1, x2, dz):
+        """Deterministic weight gradient (fixed-order sums in a workspace that
+        grows to the largest layer's need)."""
         L = next(l for l in self.layers if l.name == name)
-        conv_wgrad(x1, x2, dz, L.cout, L.ksize, self.g[name], self.gbias[name])
+        need = wgrad_workspace_size(x1, x2, L.cout, L.ksize)
+        if self.wg_ws is None or self.wg_ws.numel() < need:
+            self.wg_ws = torch.empty(need, dtype=torch.uint8, device=x1.device)
+        conv_wgrad(x1, x2, dz, L.cout, L.ksize, self.g[name], self.gbias[name], workspace=self.wg_ws)
 
     def backward(self, dout: torch.Tensor):
         """dout: BF16 [D][H][W][32] gradient at the head output.  Fills the

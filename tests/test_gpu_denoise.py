@@ -77,6 +77,17 @@ def test_conv_forward_and_gradients(dn, shape):
     dn.conv_wgrad(x1, x2, dev(dz), cout, k, dw, db)
     assert rel(dw.double().cpu(), wr.grad) < 1e-5
     assert rel(db.double().cpu(), dz.sum(dim=(0, 1, 2))) < 1e-5
+    # workspace variant: same result within rounding, bitwise reproducible
+    ws = torch.empty(dn.wgrad_workspace_size(x1, x2, cout, k), dtype=torch.uint8, device="cuda")
+    runs = []
+    for _ in range(2):
+        dw2 = torch.zeros_like(dw)
+        db2 = torch.zeros_like(db)
+        dn.conv_wgrad(x1, x2, dev(dz), cout, k, dw2, db2, workspace=ws)
+        runs.append((dw2, db2))
+    assert rel(runs[0][0].double().cpu(), wr.grad) < 1e-5
+    assert rel(runs[0][1].double().cpu(), dz.sum(dim=(0, 1, 2))) < 1e-5
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
 
 
 def test_pool_and_upsample(dn):
@@ -206,3 +217,24 @@ def test_inference_forward_equals_training_forward(dn):
     b = net.forward(feat, keep=False)
     assert b.shape[-1] == dn.NOUT
     assert torch.equal(a[..., :dn.NOUT].contiguous(), b)
+
+
+def test_training_is_bitwise_reproducible(dn):
+    """Two networks from the same seed trained on the same pairs end with
+    bitwise-identical weights (every sum in the backward pass runs in a
+    fixed order)."""
+    g = torch.Generator().manual_seed(21)
+    D = H = W = 16
+    clean = torch.rand(D, H, W, generator=g) ** 4
+    noisy = (clean * (1 + 0.5 * torch.randn(D, H, W, generator=g))).clamp_min(0).cuda()
+    kext = clean.cuda() * 0.02
+    s = dn.field_scale(noisy, noisy)
+    feat, base = dn.features(noisy, noisy, kext, 0.1 * kext, 20.0, s)
+    target = torch.stack([clean / s, clean / s], dim=-1).float().cuda().contiguous()
+    nets = [dn.Denoiser(base=32, seed=5) for _ in range(2)]
+    for net in nets:
+        for _ in range(5):
+            dn.train_step(net, feat, base, target, 1e-3)
+    for k in nets[0].p:
+        assert torch.equal(nets[0].p[k], nets[1].p[k]), k
+        assert torch.equal(nets[0].bias[k], nets[1].bias[k]), k

@@ -119,3 +119,23 @@ def test_product_path_has_no_fallback():
             rt3d.load(os.path.join(ROOT, "does_not_exist.so"))
         finally:
             rt3d._lib = saved
+
+
+def test_denoiser_wgrad_workspace_checks(lib):
+    """The deterministic weight gradient's workspace size is a host
+    computation (0 for bad shapes) and a too small or missing workspace is
+    rejected before any launch."""
+    from paper_2208_05247_amd import denoise as dn
+    dn.load()
+    good = dn._Conv(8, 8, 32, 32, 16, 64, 3, 0, 0)
+    n = lib.rt3d_dn_wgrad_workspace_size(ctypes.byref(good))
+    # per-chunk partials of 64 x 27 x 48 weights, then 64 bias partials per block
+    assert n >= 64 * 27 * 48 * 4 and n % 4 == 0
+    for bad in (dn._Conv(8, 8, 32, 8, 0, 64, 3, 0, 0), dn._Conv(8, 8, 32, 32, 0, 40, 3, 0, 0),
+                dn._Conv(8, 8, 32, 32, 0, 64, 2, 0, 0), dn._Conv(8, 8, 32, 32, 0, 64, 3, 1, 0)):
+        assert lib.rt3d_dn_wgrad_workspace_size(ctypes.byref(bad)) == 0
+    fake = ctypes.c_void_p(256)  # never dereferenced: the host checks reject first
+    f = lib.rt3d_dn_conv3d_wgrad_ws
+    assert f(ctypes.byref(good), fake, fake, fake, fake, None, fake, n - 1, None) == 1
+    assert f(ctypes.byref(good), fake, fake, fake, fake, None, None, n, None) == 1
+    assert f(ctypes.byref(good), fake, None, fake, fake, None, fake, n, None) == 1   # c2 > 0 needs x2

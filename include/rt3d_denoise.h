@@ -12,7 +12,8 @@
  * Conventions (all pointers are DEVICE pointers owned by the caller; every
  * call is asynchronous on `stream`, a hipStream_t passed as void*):
  *   activations  BF16 (uint16 bits) channels-last [D][H][W][C], C a multiple
- *                of 16;
+ *                of 16 (or exactly 4 for the packed first layer, see
+ *                rt3d_dn_conv3d_fwd);
  *   weights      BF16 [Cout][k^3][Cin] (k = 1 or 3), Cout a multiple of 32;
  *                FP32 master copies, gradients and Adam moments of the same
  *                shape; biases FP32 [Cout];
@@ -51,6 +52,9 @@ typedef struct {
 const char* rt3d_dn_last_error(void);
 
 /* y = act(conv(concat(x1, x2), w) + bias); act = ReLU if relu != 0.
+ * c1 is a multiple of 16, or exactly 4 for a 3x3x3 convolution to 32
+ * outputs with no second input, no upsampling and o1 = 32 (the first layer:
+ * x1 [vox][4], w [32][27][4]; three x-taps share one MFMA K-chunk).
  * Output channels [0, o1) go to y1 ([vox][o1]), [o1, cout) to y2
  * ([vox][cout - o1], o1 a multiple of 32).  If yf is not NULL the FP32
  * values of channels [0, yf_cols) are also written to yf [vox][yf_cols] (y1
@@ -121,7 +125,7 @@ rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* strea
 
 /* Network input per voxel: channel 0 = hdir/scale, 1 = hdif/scale,
  * 2 = ln(1 + 20 k_ext dz), 3 = ln(1 + 200 k_abs dz), channels 4..cpad-1 = 0
- * (feat BF16 [vox][cpad]); base FP32 [vox][2] = (hdir/scale, hdif/scale), the
+ * (feat BF16 [vox][cpad], cpad 4 or a multiple of 16); base FP32 [vox][2] = (hdir/scale, hdif/scale), the
  * residual the network corrects.  hdir, hdif: FP32 heating fields; k_ext,
  * k_abs: FP32 [vox] extinction and absorption coefficients (m^-1). */
 rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,

@@ -333,6 +333,84 @@ __global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
     }
 }
 
+// First layer: 3x3x3 convolution of 4 input channels to 32 outputs, input
+// [vox][4] (8 bytes per voxel), weights [32][27][4].  One MFMA K-chunk of 16
+// holds the three x-taps of one (z, y) tap pair: A = channels 0-3 of voxels
+// x-1, x, x+1 and four zeros, B = the matching 12 weights and four zeros, so
+// a row takes 9 MFMAs instead of 27 of 16 mostly-zero channels.  Tile and
+// reuse as in conv3_c32_kernel (16 rows x 32 voxels, 4 rows per wave, every
+// staged input row fed to all output rows that use it).
+__global__ void __launch_bounds__(256) conv3_c4_kernel(const ConvArgs a) {
+    __shared__ uint2 tile[kHaloVox32];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, half = lane >> 5;
+    const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY32 - 1) / kTY32;
+    long b = blockIdx.x;
+    const int txi = (int)(b % tiles_x);
+    b /= tiles_x;
+    const int tyi = (int)(b % tiles_y);
+    const int zz = (int)(b / tiles_y);
+    const int x0 = txi * kTX, y0 = tyi * kTY32;
+    const int row0 = 4 * wave;
+    for (int v = threadIdx.x; v < kHaloVox32; v += 256) {
+        const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
+        uint2 val = make_uint2(0u, 0u);
+        if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D)
+            val = *(const uint2*)(a.x1 + (((long)z * a.H + y) * a.W + x) * 4);
+        tile[v] = val;
+    }
+    // B fragments of the 9 (z, y) tap pairs: lane half 0 holds taps dx = 0, 1,
+    // half 1 tap dx = 2 and zeros
+    uint4 bv[9];
+    const uint16_t* wrow = a.w + (long)m * 27 * 4;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const uint2 lo = *(const uint2*)(wrow + (q * 3 + 2 * half) * 4);
+        const uint2 hi = half ? make_uint2(0u, 0u) : *(const uint2*)(wrow + (q * 3 + 1) * 4);
+        bv[q] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    }
+    __syncthreads();
+    f32x16 acc[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[o][e] = 0.0f;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const int i = (dz * kHaloY32 + row0 + r) * kHaloX + m;  // voxel x-1 of output column m
+            const uint2 lo = tile[i + 2 * half];
+            const uint2 hi = half ? make_uint2(0u, 0u) : tile[i + 1];
+            const uint4 av = make_uint4(lo.x, lo.y, hi.x, hi.y);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int dy = r - o;
+                if (dy >= 0 && dy <= 2)
+                    acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[dz * 3 + dy]), acc[o],
+                                                                     0, 0, 0);
+            }
+        }
+    const int n = m;
+    const float bias = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int y = y0 + row0 + o;
+        if (y >= a.H) continue;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
+            if (x >= a.W) continue;
+            float v = acc[o][e] + bias;
+            if (a.relu) v = fmaxf(v, 0.0f);
+            const long vox = ((long)zz * a.H + y) * a.W + x;
+            if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
+            if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
+        }
+    }
+}
+
 // wt[ci][taps-1-t][co] = w[co][t][ci]  (data gradient = convolution of the
 // output gradient with the flipped, transposed kernel)
 __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int cout, int cin,
@@ -624,7 +702,10 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
                                const float* bias, int32_t relu, uint16_t* y1, uint16_t* y2, int32_t o1, float* yf,
                                void* stream) {
     if (!c || !x1 || !w || (c->c2 > 0 && !x2) || (!y1 && !yf)) return RT3D_EINVAL;
-    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16) return RT3D_EINVAL;
+    // 4 input channels: only the first layer's packed form
+    const bool four = c->c1 == 4 && c->c2 == 0 && c->ksize == 3 && c->cout == 32 && !c->up1 && o1 == 32;
+    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || (c->c1 % 16 && !four) || c->c2 < 0 || c->c2 % 16)
+        return RT3D_EINVAL;
     if (c->cout <= 0 || c->cout % 32 || (c->ksize != 1 && c->ksize != 3)) return RT3D_EINVAL;
     if (o1 <= 0 || o1 > c->cout || o1 % 32 || (o1 < c->cout && !y2)) return RT3D_EINVAL;
     if (c->up1 && (c->ksize != 3 || c->D % 2 || c->H % 2 || c->W % 2)) return RT3D_EINVAL;
@@ -635,7 +716,11 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
     a.D = c->D; a.H = c->H; a.W = c->W; a.cout = c->cout; a.relu = relu ? 1 : 0;
     a.up1 = c->up1 ? 1 : 0;
     a.yf_cols = c->yf_cols ? c->yf_cols : c->cout;
-    if (c->ksize == 3 && c->cout == 32) {
+    if (four) {
+        const long tiles = (long)c->D * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
+        if (tiles > 0x7fffffffL) return RT3D_EINVAL;
+        hipLaunchKernelGGL(conv3_c4_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
+    } else if (c->ksize == 3 && c->cout == 32) {
         const long tiles = (long)c->D * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
         if (tiles > 0x7fffffffL) return RT3D_EINVAL;
         hipLaunchKernelGGL(conv3_c32_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
@@ -826,7 +911,8 @@ rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* strea
 
 rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
                              float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream) {
-    if (!hdir || !hdif || !k_ext || !k_abs || !feat || !base || cpad < 16 || cpad % 16 || !(scale > 0.0f))
+    if (!hdir || !hdif || !k_ext || !k_abs || !feat || !base || (cpad != 4 && (cpad < 16 || cpad % 16)) ||
+        !(scale > 0.0f))
         return RT3D_EINVAL;
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, hdir, hdif, k_ext,
                        k_abs, dz, 1.0f / scale, (size_t)nvox, cpad, feat, base);

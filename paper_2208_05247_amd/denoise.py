@@ -256,13 +256,23 @@ class Denoiser:
         return y
 
     def forward(self, feat: torch.Tensor, keep: bool = False) -> torch.Tensor:
-        """feat: BF16 [D][H][W][16]; returns the FP32 head output [D][H][W][32]
-        with keep (training) or its NOUT used channels [D][H][W][2]."""
-        D, H, W, _ = feat.shape
+        """feat: BF16 [D][H][W][16], or [D][H][W][4] for inference (the first
+        layer then runs packed: three x-taps per MFMA K-chunk); returns the
+        FP32 head output [D][H][W][32] with keep (training) or its NOUT used
+        channels [D][H][W][2]."""
+        D, H, W, cf = feat.shape
         if D % 8 or H % 8 or W % 8:
             raise ValueError("grid dimensions must be multiples of 8 (three pooling levels)")
+        if cf == 4 and keep:
+            raise ValueError("training needs the 16-channel features")
         a = {"x0": feat}
-        a["e0"] = self._conv("e0", feat)
+        if cf == 4:
+            L = self.layers[0]
+            a["e0"] = bf16_empty(D, H, W, L.cout)
+            conv_fwd(feat, None, self.pb["e0"][:, :, :4].contiguous(), self.bias["e0"], L.relu, L.cout, L.ksize,
+                     y1=a["e0"])
+        else:
+            a["e0"] = self._conv("e0", feat)
         a["p0"] = pool2(a["e0"])
         a["e1"] = self._conv("e1", a["p0"])
         a["p1"] = pool2(a["e1"])
@@ -371,13 +381,15 @@ class Denoiser:
 # ---------------------------------------------------------------------------
 
 def features(hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, k_abs: torch.Tensor, dz: float,
-             scale: float):
-    """BF16 features [D][H][W][16] and FP32 residual base [D][H][W][2]."""
+             scale: float, cpad: int = CPAD):
+    """BF16 features [D][H][W][cpad] (4 used; cpad 16 for training, 4 for
+    the packed first layer of inference) and FP32 residual base
+    [D][H][W][2]."""
     D, H, W = hdir.shape
-    feat = bf16_empty(D, H, W, CPAD)
+    feat = bf16_empty(D, H, W, cpad)
     base = torch.empty(D, H, W, NOUT, dtype=torch.float32, device=hdir.device)
     _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), _p(k_abs), float(dz), float(scale), hdir.numel(),
-                                   CPAD, _p(feat), _p(base), _s()), "rt3d_dn_features")
+                                   cpad, _p(feat), _p(base), _s()), "rt3d_dn_features")
     return feat, base
 
 
@@ -409,7 +421,7 @@ def denoise(net: Denoiser, hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.
             dz: float):
     """Inference: denoised (hdir, hdif), same units as the inputs."""
     s = field_scale(hdir, hdif)
-    feat, base = features(hdir, hdif, k_ext, k_abs, dz, s)
+    feat, base = features(hdir, hdif, k_ext, k_abs, dz, s, cpad=4)
     out = net.forward(feat)
     pred, _, _ = mse(out, base, None, want_grad=False)
     od, of = torch.empty_like(hdir), torch.empty_like(hdif)

@@ -238,3 +238,32 @@ def test_training_is_bitwise_reproducible(dn):
     for k in nets[0].p:
         assert torch.equal(nets[0].p[k], nets[1].p[k]), k
         assert torch.equal(nets[0].bias[k], nets[1].bias[k]), k
+
+
+def test_packed_first_layer(dn):
+    """The first layer with 4 input channels (three x-taps per MFMA K-chunk)
+    against the FP64 convolution, partial tiles included, and the inference
+    forward from 4-channel features against the 16-channel one (same
+    products, other summation order in the first layer)."""
+    g = torch.Generator().manual_seed(9)
+    for D, H, W in ((3, 20, 37), (2, 16, 32)):
+        x = bf(torch.randn(D, H, W, 4, generator=g, dtype=torch.float64))
+        w = bf(torch.randn(32, 27, 4, generator=g, dtype=torch.float64) * 0.2)
+        b = torch.randn(32, generator=g, dtype=torch.float64) * 0.1
+        yf = torch.empty(D, H, W, 32, dtype=torch.float32, device="cuda")
+        y = torch.empty(D, H, W, 32, dtype=torch.bfloat16, device="cuda")
+        dn.conv_fwd(x.to(torch.bfloat16).cuda(), None, w.to(torch.bfloat16).cuda(), b.float().cuda(), True, 32, 3,
+                    y1=y, yf=yf)
+        ref = torch.relu(dr.conv(x.permute(3, 0, 1, 2).unsqueeze(0), w, b.float().double(), 3))[0].permute(1, 2, 3, 0)
+        assert rel(yf.double().cpu(), ref) < 1e-5
+        assert torch.allclose(y.double().cpu(), bf(yf.double().cpu()))
+    net = dn.Denoiser(base=32, seed=6)
+    hd = torch.rand(16, 16, 24, generator=g).cuda()
+    hf = torch.rand(16, 16, 24, generator=g).cuda()
+    ke = torch.rand(16, 16, 24, generator=g).cuda() * 0.02
+    f16, base = dn.features(hd, hf, ke, 0.1 * ke, 20.0, 1.0)
+    f4, base4 = dn.features(hd, hf, ke, 0.1 * ke, 20.0, 1.0, cpad=4)
+    assert torch.equal(f16[..., :4].contiguous(), f4) and torch.equal(base, base4)
+    a = net.forward(f16)
+    b4 = net.forward(f4)
+    assert rel(b4.double().cpu(), a.double().cpu()) < 2e-2

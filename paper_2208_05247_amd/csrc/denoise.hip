@@ -3,16 +3,19 @@
 // produced by the tracer.  Declared in include/rt3d_denoise.h.
 //
 // Conventions: activations are BF16 channels-last [D][H][W][C] (C a multiple
-// of 16); weights BF16 [Cout][KS^3][Cin] with FP32 master copies; all
-// products accumulate in FP32 on the matrix cores.
+// of 16, or 4 for the first layer's input); weights BF16 [Cout][KS^3][Cin]
+// with FP32 master copies; all products accumulate in FP32 on the matrix
+// cores.
 //
-// Convolution = implicit GEMM on v_mfma_f32_32x32x16_bf16: one wave owns 32
-// consecutive voxels along x (the GEMM rows) and 32 output channels (the
-// columns); the reduction runs over the KS^3 taps and 16-channel chunks.  A
-// lane feeds the A operand with 8 channels of one voxel (one 16-byte load,
-// zero outside the domain) and the B operand with 8 input channels of one
-// output channel's weights.  The accumulator of lane l, element r holds row
-// 8*(r/4) + 4*(l/32) + r%4, column l%32.
+// Convolution = implicit GEMM on v_mfma_f32_32x32x16_bf16: GEMM rows are 32
+// consecutive voxels along x, columns 32 output channels, and the reduction
+// runs over the KS^3 taps and 16-channel chunks.  A lane feeds the A operand
+// with 8 channels of one voxel (zero outside the domain) and the B operand
+// with 8 input channels of one output channel's weights.  The accumulator of
+// lane l, element r holds row 8*(r/4) + 4*(l/32) + r%4, column l%32.
+// 3x3x3 layers run from an input halo staged in LDS (conv3_tiled_kernel,
+// conv3_c32_kernel, conv3_c4_kernel); the 1x1x1 head uses conv_fwd_kernel,
+// one wave per 32 x 32 output tile with its operands read directly.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>

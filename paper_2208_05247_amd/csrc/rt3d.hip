@@ -10,10 +10,13 @@
 // Design for CDNA4 (not the paper's CUDA design):
 //   * persistent kernel, one photon per lane, lanes refilled from a
 //     per-wave pool of photon ids that is topped up with one global atomic
-//     per pool, so divergent photon lifetimes do not idle the wave;
-//   * one loop pass = one acceleration-grid cell: either the tentative
-//     collision inside it, or a crossing into the next cell (surface / top
-//     handled at the crossing), so all lanes do comparable work per pass;
+//     per pool, so divergent photon lifetimes do not idle the wave; a wave
+//     refills once 16 of its lanes are idle, so the emission code runs for
+//     many lanes at once;
+//   * one loop pass = at most a few acceleration-grid crossings (3 by
+//     default) and then the event reached, if any (tentative collision,
+//     surface, top): a lane on a long clear-sky walk does not hold its wave
+//     through all of it;
 //   * majorants staged in LDS when they fit, else read through L1/L2;
 //   * integer weights (units of 2^-31) and uint64 tallies: order-independent
 //     atomics, bitwise-reproducible results and an exactly closing ledger;

@@ -4,7 +4,8 @@ encoder-decoder built from its kernels.
 Network (4 resolution levels, 32 base channels, BF16 weights and
 activations, FP32 accumulation on the matrix cores):
 
-  x0 [16: hdir/s, hdif/s, ln(1+20 k_ext dz), ln(1+200 k_abs dz), 0...]
+  x0 [hdir/s, hdif/s, ln(1+20 k_ext dz), ln(1+200 k_abs dz)], padded to 16
+     channels for training, 4 for inference (packed first layer)
   e0 = relu(conv3 x0 -> 32)           level 0
   e1 = relu(conv3 pool(e0) -> 64)     level 1
   e2 = relu(conv3 pool(e1) -> 128)    level 2

@@ -15,7 +15,8 @@ denoised field reaches 5 %, timed as batched tracing + network inference.
 
 The denoiser is trained on pairs the tracer generates: random cumulus
 fields on the evaluation grid spacing, random sun, surface albedo and
-g-point sets, inputs at 64-1024 photons per column, targets at 8192.
+g-point sets, inputs at 64-1024 photons per column, targets at 16384
+(training is bitwise reproducible, so is the whole result).
 
   python -m paper_2208_05247_amd.experiment [--quick] [--out result.json]
 """

@@ -13,6 +13,10 @@ paper's convergence law), kernel time is fitted linearly in N, and the time
 at eps = 5 % follows.  Denoised: the smallest photons-per-column whose
 denoised field reaches 5 %, timed as batched tracing + network inference.
 
+Photons enter as the domain-top flux of the clear-sky two-stream column of
+every g-point (photon shares proportional to its total downward flux there,
+per-g-point diffuse fraction), in training and evaluation alike.
+
 The denoiser is trained on pairs the tracer generates: random cumulus
 fields on the evaluation grid spacing, random sun, surface albedo and
 g-point sets, inputs at 64-1024 photons per column, targets at 16384
@@ -35,7 +39,7 @@ from . import denoise as dn
 from . import rt3d
 from . import synthetic as syn
 
-F_TOD = 1000.0     # W m^-2, nominal downward flux at the domain top
+F_TOD = 1000.0     # W m^-2, nominal total (direct + diffuse) downward flux at the domain top
 CP = 1004.0        # J kg^-1 K^-1
 TARGET_EPS = 0.05
 
@@ -57,15 +61,46 @@ def multinomial_counts(weights, total, seed):
     return np.random.default_rng(seed).multinomial(int(total), weights).astype(np.uint64)
 
 
-class Tracer:
-    """Batched tracing of one scene into heating-rate fields (K/day)."""
+def top_of_domain_entry(wl: "syn.BatchedWorkload", n_above: int = 32):
+    """The flux entering the domain top (sec. 2.3, initialisation): every
+    g-point's clear-sky column (its gas levels continued up to 60 km) is
+    solved with the two-stream kernel for its TOA share of the flux, the sun
+    at the scene's zenith angle and the domain's mean albedo.  Returns the
+    photon shares (proportional to each g-point's total downward flux at the
+    domain top, so every photon carries the same energy), the FP32 device
+    tensor of each g-point's diffuse fraction there, and a summary (flux at
+    the domain top over the TOA flux, share-weighted diffuse fraction)."""
+    m = wl.medium
+    tau, ssa, g = syn.clear_sky_columns(m, n_above=n_above)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    alb = np.full(m.n_gpoints, float(m.albedo.mean()))
+    out = rt3d.two_stream(dev(tau), dev(ssa), dev(g), dev(alb), math.cos(math.radians(wl.sza)), n_above,
+                          flux_toa=dev(m.weights))
+    ftod = out["tod_flux"].cpu().numpy()
+    shares = ftod / ftod.sum()
+    fd = out["tod_diffuse_fraction"]
+    info = {"tod_over_toa_flux": float(ftod.sum() / (m.weights.sum() * math.cos(math.radians(wl.sza)))),
+            "mean_diffuse_fraction": float((shares * fd.double().cpu().numpy()).sum())}
+    return shares, fd, info
 
-    def __init__(self, wl: "syn.BatchedWorkload", brick=(8, 8, 8)):
+
+class Tracer:
+    """Batched tracing of one scene into heating-rate fields (K/day).  With
+    `tod_entry` photons enter as the two-stream flux at the domain top
+    (shares and diffuse fraction per g-point), else all along the sun beam
+    with the TOA flux weights as shares."""
+
+    def __init__(self, wl: "syn.BatchedWorkload", brick=(8, 8, 8), tod_entry: bool = True):
         self.wl = wl
         self.m = wl.medium
         self.grid = self.m.grid
         self.dm = rt3d.DeviceBatchedMedium.from_host(self.m)
         self.brick = brick
+        if tod_entry:
+            self.shares, self.fd, self.entry = top_of_domain_entry(wl)
+        else:
+            self.shares, self.fd = np.asarray(self.m.weights, dtype=np.float64), None
+            self.entry = {"tod_over_toa_flux": 1.0, "mean_diffuse_fraction": 0.0}
         opt = rt3d.options(brick=brick)
         self.ws = rt3d.alloc_workspace(rt3d.workspace_size_batched(self.grid, self.m.n_gpoints, opt))
         self.out = rt3d.alloc_tallies(self.grid)
@@ -75,7 +110,7 @@ class Tracer:
     def k_mean(self):
         """Flux-weighted extinction and absorption fields (network inputs)."""
         if self.k_ext is None:
-            w = self.m.weights[:, None]
+            w = self.shares[:, None]
             kg = (w * self.m.k_gas.astype(np.float64)).sum(axis=0)
             kga = (w * self.m.k_gas.astype(np.float64) * (1.0 - self.m.ssa_gas.astype(np.float64))).sum(axis=0)
             kc = self.m.k_cloud.astype(np.float64)
@@ -95,10 +130,10 @@ class Tracer:
         raw = None
         for k in range(nchunk):
             part = total // nchunk + (1 if k < total % nchunk else 0)
-            counts = multinomial_counts(self.m.weights, part, seed + 1000 * k)
+            counts = multinomial_counts(self.shares, part, seed + 1000 * k)
             raw = rt3d.trace_batched(self.dm, self.wl.sza, self.wl.azimuth, counts, seed + 1000 * k,
                                      brick=self.brick, out=self.out, workspace=self.ws, timed=True,
-                                     accumulate=k > 0)
+                                     accumulate=k > 0, gpoint_diffuse=self.fd)
             kms += rt3d.last_trace_ms()
         fin = rt3d.finalize(self.grid, raw, total, layer_scale=self.ls)
         return fin["abs_dir"], fin["abs_dif"], kms, total
@@ -125,7 +160,8 @@ def scene(seed: int, nx: int, ny: int, nz: int, dx: float, dz: float, sza=None, 
 
 
 def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: int, dx: float, dz: float,
-          low=(64, 128, 192, 256, 384, 512, 1024), high: int = 8192, lr: float = 1e-3, seed0: int = 0):
+          low=(64, 128, 192, 256, 384, 512, 1024), high: int = 8192, lr: float = 1e-3, seed0: int = 0,
+          tod_entry: bool = True):
     """Train on tracer-generated pairs: one new random scene per field,
     `steps_per_field` noisy realisations against one high-photon target."""
     losses = []
@@ -135,7 +171,7 @@ def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: in
     total_steps = n_fields * steps_per_field
     for f in range(n_fields):
         wl = scene(seed0 + f, nx, nx, nz, dx, dz)
-        tr = Tracer(wl)
+        tr = Tracer(wl, tod_entry=tod_entry)
         tdir, tdif, _, _ = tr.heating(high, seed=10_000_000 * (f + 1))
         kext, kabs = tr.k_mean()
         for s in range(steps_per_field):
@@ -159,8 +195,8 @@ def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: in
 
 
 def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
-             low=(64, 128, 192, 256, 320, 384, 512, 768, 1024)):
-    tr = Tracer(wl)
+             low=(64, 128, 192, 256, 320, 384, 512, 768, 1024), tod_entry: bool = True):
+    tr = Tracer(wl, tod_entry=tod_entry)
     g = tr.grid
     log("reference halves ...")
     half = ref_per_col // 2
@@ -207,7 +243,8 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
             break
     res = {"plain_fit": {"a": a, "photons_per_column_at_5pct": n5, "t0_ms": float(t0), "ms_per_unit_N": float(c),
                          "time_to_5pct_ms": t_plain},
-           "plain_sweep": plain, "denoised": den, "reference_photons_per_column": ref_per_col}
+           "plain_sweep": plain, "denoised": den, "reference_photons_per_column": ref_per_col,
+           "entry": "two-stream top of domain" if tod_entry else "sun beam, TOA flux weights", **tr.entry}
     if reached:
         t_dn = reached["trace_ms"] + reached["inference_ms"]
         res["denoised_time_to_5pct_ms"] = t_dn
@@ -267,6 +304,9 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--train-fields", type=int, default=400)
     ap.add_argument("--steps-per-field", type=int, default=8)
+    ap.add_argument("--sun-entry", action="store_true",
+                    help="all photons along the sun beam with the TOA flux weights as g-point shares "
+                         "(instead of the two-stream flux at the domain top)")
     ap.add_argument("--config3", action="store_true",
                     help="train/evaluate on 256x256x96 fields (4-photon inputs, 1024-photon targets) instead")
     args = ap.parse_args()
@@ -282,10 +322,10 @@ def main():
     log(f"denoiser parameters: {net.n_params()}")
     t0 = time.perf_counter()
     losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz,
-                           high=2048 if args.quick else 16384)
+                           high=2048 if args.quick else 16384, tod_entry=not args.sun_entry)
     train_s = time.perf_counter() - t0
     wl = scene(99_999, ev_nx, ev_nx, nz, dx, dz, sza=60.0, az=0.0, photons=1 << 30)
-    res = evaluate(net, wl, ref)
+    res = evaluate(net, wl, ref, tod_entry=not args.sun_entry)
     res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,
                 "ms_per_train_step": 1e3 * step_s,
                 "final_train_loss": float(np.mean(losses[-20:])),

@@ -291,3 +291,25 @@ def test_two_stream_tod_end_to_end_parity(rt3d):
         frac, n_dense, _, dense, z = compare_batches(np.stack(gpu[k]), np.stack(ora[k]))
         say("tod parity", k, round(frac, 5), n_dense)
         assert frac >= 0.998, k
+
+
+def test_experiment_entry_shares_and_fractions(rt3d):
+    """The time-to-5 % experiment's entry: photon shares are each g-point's
+    total downward flux at the domain top over their sum, and the diffuse
+    fractions those of the two-stream column (FP64 oracle), for a 112
+    g-point scene at a slanted sun."""
+    from paper_2208_05247_amd import experiment as ex
+    wl = ex.scene(77, 32, 32, 32, 25.0, 20.0, sza=60.0, az=0.0)
+    shares, fd, info = ex.top_of_domain_entry(wl)
+    m = wl.medium
+    tau, ssa, g = syn.clear_sky_columns(m, n_above=32)
+    mu0 = float(np.cos(np.radians(60.0)))
+    alb = float(m.albedo.mean())
+    ref = [ots.top_of_domain(tau[n], ssa[n], g[n], mu0, alb, 32, flux_toa=m.weights[n])
+           for n in range(m.n_gpoints)]
+    tot = np.array([r[0] for r in ref])
+    assert np.allclose(shares, tot / tot.sum(), rtol=1e-9, atol=0.0)
+    assert np.allclose(fd.cpu().numpy(), np.array([r[1] for r in ref], dtype=np.float32), rtol=2e-7, atol=0.0)
+    assert info["tod_over_toa_flux"] == pytest.approx(tot.sum() / (m.weights.sum() * mu0), rel=1e-9)
+    assert 0.0 < info["tod_over_toa_flux"] < 1.0 and 0.0 < info["mean_diffuse_fraction"] < 1.0
+    say("TOD/TOA flux", info["tod_over_toa_flux"], "mean diffuse fraction", info["mean_diffuse_fraction"])

@@ -206,9 +206,12 @@ struct Local {
     float ke, ka, ks, kc, g;
 };
 
+// Factored: `clear` marks a brick without cloud, whose cell records are all
+// zero in the fields used here, so the gather is skipped.
 template <bool kFactored>
-__device__ __forceinline__ Local local_props(const TraceParams& P, int gp, uint32_t cell, int k) {
-    const float4 c = P.cells[cell];
+__device__ __forceinline__ Local local_props(const TraceParams& P, int gp, uint32_t cell, int k, bool clear) {
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!kFactored || !clear) c = P.cells[cell];
     Local L;
     if (!kFactored) {
         L.ke = c.x;
@@ -428,7 +431,9 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             if (iters >= P.max_iters) { outcome = kCapped; break; }
             if (walked >= P.max_walk) { outcome = kWalking; break; }
             ++iters;
+            // factored majorants carry the brick's "no cloud" flag in the sign bit
             K = kLds ? s_maj[(bk * P.my + bj) * P.mx + bi] : P.majorant[maj_base + (bk * P.my + bj) * P.mx + bi];
+            const float Km = fabsf(K);
             const float x0 = (float)bi * P.cx, y0 = (float)bj * P.cy, z0 = (float)bk * P.cz;
             float tx = INFINITY, ty = INFINITY, tz = INFINITY;
             if (ux > 0.f) tx = (x0 + P.cx - px) * rcp(ux);
@@ -444,15 +449,15 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             float s_exit = tx;
             if (ty < s_exit) { s_exit = ty; axis = 1; }
             if (tz < s_exit) { s_exit = tz; axis = 2; }
-            if (K * s_exit >= tau) {
-                const float sc = tau * rcp(K);
+            if (Km * s_exit >= tau) {
+                const float sc = tau * rcp(Km);
                 px += sc * ux;
                 py += sc * uy;
                 pz += sc * uz;
                 outcome = kCollision;
                 break;
             }
-            tau -= K * s_exit;
+            tau -= Km * s_exit;
             px += s_exit * ux;
             py += s_exit * uy;
             pz += s_exit * uz;
@@ -493,7 +498,9 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             const int j = cell_ix(py, P.inv_dy, bj, P.by);
             const int k = cell_ix(pz, P.inv_dz, bk, P.bz);
             const uint32_t cell = (uint32_t)((k * P.ny + j) * P.nx + i);
-            const Local L = local_props<kFactored>(P, gp, cell, k);
+            const bool clear = kFactored && __float_as_uint(K) >> 31;
+            K = fabsf(K);
+            const Local L = local_props<kFactored>(P, gp, cell, k, clear);
             const float iK = rcp(K);
             ++n_coll;
             if (L.ka > 0.f) {
@@ -679,7 +686,9 @@ __global__ void layer_max_kernel(const float4* __restrict__ cells, uint32_t* __r
 
 // Factored majorant, step 2: K[n][bk][bj][bi] = max over the levels k of
 // brick layer bk of (k_gas[n][k] + layer[k][bj][bi]).  FP32 addition is
-// monotonic, so this equals the largest k_gas + k_cloud of the cells.
+// monotonic, so this equals the largest k_gas + k_cloud of the cells.  A
+// brick with no cloud extinction in any cell stores -K (sign bit set, -0 for
+// K = 0): the tracer reads |K| and skips the cell gather there.
 __global__ void gas_majorant_kernel(const uint32_t* __restrict__ layer, const float2* __restrict__ gas,
                                     float* __restrict__ maj, int ngp, int nz, int mx, int my, int bz) {
     const int mz = nz / bz;
@@ -691,12 +700,15 @@ __global__ void gas_majorant_kernel(const uint32_t* __restrict__ layer, const fl
         const size_t col = b % ((size_t)mx * my);
         const int bk = (int)(b / ((size_t)mx * my));
         float m = 0.0f;
+        uint32_t cloud = 0;
         for (int q = 0; q < bz; ++q) {
             const int k = bk * bz + q;
-            const float v = gas[(size_t)gp * nz + k].x + __uint_as_float(layer[(size_t)k * mx * my + col]);
+            const uint32_t lc = layer[(size_t)k * mx * my + col];
+            const float v = gas[(size_t)gp * nz + k].x + __uint_as_float(lc);
             m = v > m ? v : m;
+            cloud |= lc;
         }
-        maj[t] = m;
+        maj[t] = __uint_as_float(__float_as_uint(m) | (cloud ? 0u : 0x80000000u));
     }
 }
 

@@ -101,9 +101,13 @@ def test_launch_options_do_not_change_tallies(rt3d, kw):
 
 def test_batched_parity_vs_oracle(rt3d):
     """Broadband tallies of 6 g-points (gas optical depth 1e-3..50) vs the
-    oracle traced per g-point on materialised fields, 32 batches each."""
+    oracle traced per g-point on materialised fields, 32 batches each.  The
+    scene has bricks without cloud (where the kernel reads no cell record)
+    and bricks with cloud."""
     wl = small_batch(n_gp=6, photons=1 << 15, seed=5)
     m = wl.medium
+    cloudy = m.k_cloud.reshape(8, 4, 8, 4, 8, 4).max(axis=(1, 3, 5)) > 0
+    assert 0.2 < 1.0 - cloudy.mean() < 0.8
     counts = [int(c) for c in wl.photons]
     total = sum(counts)
     dm = rt3d.DeviceBatchedMedium.from_host(m)

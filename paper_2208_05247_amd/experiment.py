@@ -147,6 +147,21 @@ def eps_against(h: torch.Tensor, ref_a: torch.Tensor, ref_b: torch.Tensor) -> fl
     return math.sqrt(max(mse, 0.0) / power)
 
 
+def plain_fit(photons_per_column, eps, kernel_ms, target: float = TARGET_EPS):
+    """Plain tracing's time to the target error: eps = a N^-1/2 (the Monte
+    Carlo convergence law; a = geometric mean of eps sqrt(N), i.e. least
+    squares in log space with the slope fixed at -1/2) and kernel time
+    t0 + c N (least squares).  Returns (a, c, t0, N at the target, time at
+    the target in ms)."""
+    Ns = np.asarray(photons_per_column, dtype=np.float64)
+    E = np.asarray(eps, dtype=np.float64)
+    T = np.asarray(kernel_ms, dtype=np.float64)
+    a = float(np.exp(np.mean(np.log(E * np.sqrt(Ns)))))
+    c, t0 = np.polyfit(Ns, T, 1)
+    n_target = (a / target) ** 2
+    return a, float(c), float(t0), n_target, float(t0 + c * n_target)
+
+
 def scene(seed: int, nx: int, ny: int, nz: int, dx: float, dz: float, sza=None, az=None, n_gp=112,
           photons=1 << 20):
     rng = np.random.default_rng(10_000 + seed)
@@ -211,14 +226,8 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
         e = eps_against(hd + hf, ref_a, ref_b)
         plain.append({"photons_per_column": n, "kernel_ms": kms, "eps": e})
         log(f"plain N={n}: eps {e:.4f}, kernel {kms:.1f} ms")
-    Ns = np.array([p["photons_per_column"] for p in plain], dtype=np.float64)
-    E = np.array([p["eps"] for p in plain])
-    T = np.array([p["kernel_ms"] for p in plain])
-    # eps = a N^-1/2 (least squares on eps * sqrt(N)), time = t0 + c N
-    a = float(np.exp(np.mean(np.log(E * np.sqrt(Ns)))))
-    c, t0 = np.polyfit(Ns, T, 1)
-    n5 = (a / TARGET_EPS) ** 2
-    t_plain = float(t0 + c * n5)
+    a, c, t0, n5, t_plain = plain_fit([p["photons_per_column"] for p in plain], [p["eps"] for p in plain],
+                                      [p["kernel_ms"] for p in plain])
     kext, kabs = tr.k_mean()
     den = []
     reached = None
@@ -241,7 +250,7 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
         if e <= TARGET_EPS and reached is None:
             reached = rec
             break
-    res = {"plain_fit": {"a": a, "photons_per_column_at_5pct": n5, "t0_ms": float(t0), "ms_per_unit_N": float(c),
+    res = {"plain_fit": {"a": a, "photons_per_column_at_5pct": n5, "t0_ms": t0, "ms_per_unit_N": c,
                          "time_to_5pct_ms": t_plain},
            "plain_sweep": plain, "denoised": den, "reference_photons_per_column": ref_per_col,
            "entry": "two-stream top of domain" if tod_entry else "sun beam, TOA flux weights", **tr.entry}

@@ -1,0 +1,66 @@
+"""Host logic of the time-to-5 % experiment (no GPU): the heating-rate error
+measure with the reference's own noise removed, the fit of plain tracing's
+convergence law and cost, and the photon split over g-points."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2208_05247_amd import experiment as ex  # noqa: E402
+
+
+def test_eps_with_noise_free_reference_is_relative_rms():
+    truth = torch.tensor([1.0, 2.0, 3.0, 4.0])
+    h = torch.tensor([1.0, 2.0, 3.0, 6.0])
+    # mean squared error 4/4, mean square of the reference 30/4
+    assert ex.eps_against(h, truth, truth) == pytest.approx(math.sqrt(1.0 / 7.5), rel=1e-15)
+    assert ex.eps_against(truth, truth, truth) == 0.0
+
+
+def test_eps_removes_the_reference_noise():
+    """Reference halves with independent noise of variance sigma^2 each (so
+    their mean has sigma^2 / 2): a field with error variance s^2 scores
+    s / rms(truth), the truth itself about 0, whatever sigma is (at
+    sigma = 0.5, leaving the noise in the reference's mean square would
+    lower the score by 6 %, and taking the variance of a single half
+    instead of that of their mean would drive it to 0)."""
+    g = np.random.default_rng(5)
+    n = 1 << 22
+    truth = 1.0 + 0.5 * np.sin(np.linspace(0.0, 40.0, n))
+    rms = math.sqrt(float(np.mean(truth ** 2)))
+    for sigma in (0.05, 0.5):
+        a = torch.from_numpy(truth + sigma * g.standard_normal(n))
+        b = torch.from_numpy(truth + sigma * g.standard_normal(n))
+        s = 0.1
+        h = torch.from_numpy(truth + s * g.standard_normal(n))
+        assert ex.eps_against(h, a, b) == pytest.approx(s / rms, rel=0.02)
+        assert ex.eps_against(torch.from_numpy(truth), a, b) < 0.03
+
+
+def test_plain_fit_recovers_the_convergence_law_and_cost():
+    Ns = [16, 64, 256, 1024]
+    eps = [4.2 / math.sqrt(n) for n in Ns]
+    ms = [3.0 + 1.2 * n for n in Ns]
+    a, c, t0, n5, t5 = ex.plain_fit(Ns, eps, ms)
+    assert a == pytest.approx(4.2, rel=1e-12)
+    assert c == pytest.approx(1.2, rel=1e-9) and t0 == pytest.approx(3.0, rel=1e-6)
+    assert n5 == pytest.approx((4.2 / 0.05) ** 2, rel=1e-12)
+    assert t5 == pytest.approx(3.0 + 1.2 * (4.2 / 0.05) ** 2, rel=1e-9)
+    # scattered errors: a is the geometric mean of eps sqrt(N)
+    eps2 = [2.0 / 4.0, 8.0 / 8.0]
+    a2, _, _, _, _ = ex.plain_fit([16, 64], eps2, [1.0, 2.0])
+    assert a2 == pytest.approx(math.sqrt(2.0 * 8.0), rel=1e-12)
+
+
+def test_multinomial_counts():
+    w = np.array([0.5, 0.25, 0.125, 0.125])
+    c1 = ex.multinomial_counts(w, 1 << 20, 7)
+    c2 = ex.multinomial_counts(w, 1 << 20, 7)
+    assert c1.dtype == np.uint64 and int(c1.sum()) == 1 << 20
+    assert np.array_equal(c1, c2)
+    assert not np.array_equal(c1, ex.multinomial_counts(w, 1 << 20, 8))
+    # each count within 6 binomial standard deviations of its mean
+    mean = w * (1 << 20)
+    assert np.all(np.abs(c1 - mean) < 6 * np.sqrt(mean * (1 - w)))

@@ -265,6 +265,47 @@ def denoiser_measurement(reps: int = 3) -> dict:
                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "flops_per_call": flops}}
 
 
+# Merged tally atomics per tentative collision of the tracer on the benchmark
+# field: 31.2 per photon against 44.4 tentative collisions (0.70 ~ 11/16).
+ACCESS_ATOMICS_PER_16 = 11
+
+
+def access_ceiling(ncell: int, collisions_per_launch: float, kernel_ms=None, reps: int = 2) -> dict:
+    """What the memory system delivers for the tracer's access pattern on
+    the benchmark's footprint (ncell 16-byte records, 2 x ncell uint64
+    tallies): rt3d_access_probe with as many dependent random gathers as the
+    tracer makes tentative collisions per launch, 11 of 16 followed by a
+    random 64-bit atomic add, and once without the atomics; the tracer's
+    collision rate as a fraction of that ceiling (when kernel_ms is given)."""
+    import torch
+    from paper_2208_05247_amd import rt3d
+    g = torch.Generator(device="cuda").manual_seed(3)
+    rec = torch.rand((ncell, 4), generator=g, device="cuda", dtype=torch.float32)
+    tally = torch.zeros(2 * ncell, dtype=torch.int64, device="cuda")
+    lanes = int(rt3d.load().rt3d_access_probe_lanes(0))
+    events = max(1, int(round(collisions_per_launch / lanes)))
+    rt3d.access_probe(rec, tally, 64, ACCESS_ATOMICS_PER_16, seed=1)
+    torch.cuda.synchronize()
+    rates = {}
+    for name, a16 in (("with_atomics", ACCESS_ATOMICS_PER_16), ("gathers_only", 0)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for r in range(reps):
+            rt3d.access_probe(rec, tally, events, a16, seed=r + 2)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rates[name] = (ms, lanes * events / (ms * 1e-3))
+    res = {"lanes": lanes, "gathers_per_lane": events, "atomics_per_16": ACCESS_ATOMICS_PER_16,
+           "records_bytes": ncell * 16, "tally_bytes": 2 * ncell * 8,
+           "probe_ms": rates["with_atomics"][0], "ceiling_gathers_per_s": rates["with_atomics"][1],
+           "gathers_only_per_s": rates["gathers_only"][1]}
+    if kernel_ms:
+        tracer = collisions_per_launch / (kernel_ms * 1e-3)
+        res.update({"tracer_collisions_per_s": tracer, "frac_of_ceiling": tracer / rates["with_atomics"][1]})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +320,8 @@ def main():
     ap.add_argument("--max-walk", type=int, default=0, help="brick crossings per loop iteration (0 = automatic)")
     ap.add_argument("--inference-only", action="store_true",
                     help="only time denoiser inference on the 1024x1024x128 grid (prints its JSON)")
+    ap.add_argument("--access-probe", action="store_true",
+                    help="only run the memory-access ceiling probe on the benchmark's footprint (prints its JSON)")
     ap.add_argument("--brick", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched g-point measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -295,6 +338,10 @@ def main():
         return
     if args.inference_only:
         print(json.dumps({"denoiser_inference": denoiser_measurement()}), flush=True)
+        return
+    if args.access_probe:
+        # the benchmark launch's 2^26 photons x 44.4 events, its 256x256x128 cells
+        print(json.dumps({"access_ceiling": access_ceiling(256 * 256 * 128, 44.4 * (1 << 26))}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tracer is single-GPU (photons or g-points would be "
@@ -373,6 +420,7 @@ def main():
                          "photons/column on 768x768 columns (different fields)",
     }
     if not args.no_batched:
+        res["access_ceiling"] = access_ceiling(grid.ncell, tot["collisions"] / args.steps, mean_kms)
         res["batched"] = batched_measurement(max(1, min(args.steps, 3)))
         res["sobol_entry"] = entry_measurement()
         res["two_stream_tod"] = two_stream_measurement()

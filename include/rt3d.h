@@ -381,6 +381,33 @@ rt3d_status rt3d_two_stream(int32_t n_cols, int32_t nlay, const double* tau,
                             int32_t tod_level, double* tod_flux,
                             float* tod_diffuse_fraction, void* stream);
 
+/* Memory-system ceiling of the tracer's access pattern, for measurement
+ * only (not a step of the method): a persistent grid of 1024-lane
+ * workgroups (8 waves per SIMD, as the single-g-point tracer) in which
+ * every lane performs `events` dependent random 16-byte gathers from
+ * `records` (DEVICE, n_records 16-byte records, 16-byte aligned): the index
+ * of each gather is a hash of the record the previous one returned, so a
+ * lane has one gather in flight at a time, as a photon's next collision
+ * depends on the last.  After `atomics_per_16` of every 16 gathers the lane
+ * adds 1 to tally[j] (DEVICE uint64, n_tally entries) at a random j with a
+ * 64-bit atomic, as a tentative collision deposits into the heating tallies.
+ * Indices are uniform over the arrays (bounded by n_records, n_tally).
+ * grid_blocks: workgroups (0 = two per compute unit).  sink (DEVICE FP32,
+ * n_sink entries, at least rt3d_access_probe_lanes(grid_blocks)) receives a
+ * per-lane sum of the loaded values so no gather is dead.  RT3D_EINVAL on
+ * null pointers, zero sizes, n_records or n_tally >= 2^32,
+ * atomics_per_16 > 16, records not 16-byte aligned, a short sink.
+ * Asynchronous on `stream`; time it with events on that stream. */
+rt3d_status rt3d_access_probe(const void* records, uint64_t n_records,
+                              uint64_t* tally, uint64_t n_tally,
+                              uint32_t events, uint32_t atomics_per_16,
+                              uint32_t grid_blocks, uint64_t seed, float* sink,
+                              uint64_t n_sink, void* stream);
+
+/* Lanes rt3d_access_probe launches for grid_blocks (0 = two workgroups per
+ * compute unit of the current device); 0 if the device cannot be queried. */
+uint64_t rt3d_access_probe_lanes(uint32_t grid_blocks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,7 +7,7 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", n) for n in ("rt3d.hip", "denoise.hip", "two_stream.hip")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("rt3d.hip", "denoise.hip", "two_stream.hip", "access_probe.hip")]
 LIB = os.path.join(PKG, "librt3d.so")
 ARCH = os.environ.get("RT3D_OFFLOAD_ARCH", "gfx950")
 

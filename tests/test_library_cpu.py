@@ -104,6 +104,14 @@ def test_einval_before_any_launch(lib):
     assert ts(2, 5, *args, 1.5, None, fake, fake, fake, 0, None, None, None) == rt3d.EINVAL   # mu0 > 1
     assert ts(2, 5, *args, 0.5, None, fake, fake, fake, 6, None, None, None) == rt3d.EINVAL   # level > nlay
     assert ts(2, 5, *args, 0.5, None, None, fake, fake, 0, None, None, None) == rt3d.EINVAL   # no output
+    ap = lib.rt3d_access_probe
+    assert ap(None, 16, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL            # no records
+    assert ap(fake, 0, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL             # empty
+    assert ap(fake, 1 << 32, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL       # too many records
+    assert ap(fake, 16, fake, 16, 8, 17, 4, 1, fake, 4096, None) == rt3d.EINVAL            # > 16 of 16
+    assert ap(ctypes.c_void_p(264), 16, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL  # misaligned
+    assert ap(fake, 16, fake, 16, 8, 11, 4, 1, fake, 4095, None) == rt3d.EINVAL            # short sink
+    assert lib.rt3d_access_probe_lanes(5) == 5 * 1024
 
 
 def test_product_path_has_no_fallback():

@@ -215,14 +215,15 @@ def test_more_than_2_31_photons_in_one_launch(rt3d):
         rt3d.trace(df, 0.0, 0.0, 1 << 33, 17, brick=(4, 4, 1))
 
 
-def direct_expectation(m, sza, azimuth, counts, cols):
+def direct_expectation(m, sza, azimuth, counts, cols, fd=None):
     """Expected broadband direct surface irradiance (fraction of the TOD
-    flux) of sampled columns for photon counts `counts` per g-point.  Every
-    g-point's gas is horizontally uniform, so along the straight slant path
-    of an unscattered photon its optical depth is its column optical depth
-    over mu0, exactly; the per-g-point transmittance is that factor times
-    the cloud field's, which the oracle gives as deterministic line
-    integrals over a lattice of entry points."""
+    flux) of sampled columns for photon counts `counts` per g-point, of
+    which the fractions `fd` (default 0) enter diffuse.  Every g-point's gas
+    is horizontally uniform, so along the straight slant path of an
+    unscattered photon its optical depth is its column optical depth over
+    mu0, exactly; the per-g-point transmittance is that factor times the
+    cloud field's, which the oracle gives as deterministic line integrals
+    over a lattice of entry points."""
     grid = m.grid
     kc = np.ascontiguousarray(m.k_cloud, dtype=np.float32)
     zeros = np.zeros_like(kc)
@@ -231,7 +232,8 @@ def direct_expectation(m, sza, azimuth, counts, cols):
     mu0 = np.cos(np.radians(sza))
     tau_gas = m.k_gas.astype(np.float64).sum(axis=1) * grid.dz
     share = np.asarray(counts, dtype=np.float64) / float(np.sum(counts))
-    return tc * float(np.sum(share * np.exp(-tau_gas / mu0)))
+    beam = 1.0 - (np.zeros_like(share) if fd is None else np.asarray(fd, dtype=np.float64))
+    return tc * float(np.sum(share * beam * np.exp(-tau_gas / mu0)))
 
 
 def check_direct_columns(rt3d, m, raw, total, sza, azimuth, n_cols=48, seed=0):
@@ -283,4 +285,31 @@ def test_large_combined_full_size(rt3d):
     got = np.array([sfc[j, i] for i, j in cols])
     se = np.sqrt(np.maximum(ref * (1 - ref), 1e-4) / per_col)
     say("large direct columns: max |z|", float(np.max(np.abs(got - ref) / se)))
+    assert np.all(np.abs(got - ref) <= 5 * se + 1e-3), np.c_[got, ref, se]
+
+
+def test_large_two_stream_entry_full_size(rt3d):
+    """The time-to-5 % evaluation scene as the experiment traces it: 1024 x
+    1024 x 128 cells, 112 g-points, photons split over the g-points by the
+    two-stream flux at the domain top and entering diffuse with each
+    g-point's diffuse fraction there, 2^30 photons in one launch.  Exact
+    ledger, photons per g-point as asked, and the direct irradiance of 48
+    sampled columns against the factorised expectation with the beam
+    fractions 1 - f_d."""
+    from paper_2208_05247_amd import experiment as ex
+    wl = ex.scene(99_999, 1024, 1024, 128, 25.0, 20.0, sza=60.0, az=0.0, photons=1 << 20)
+    m = wl.medium
+    shares, fd, info = ex.top_of_domain_entry(wl)
+    counts = ex.multinomial_counts(shares, 1 << 30, 77)
+    total = int(counts.sum())
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    raw = rt3d.trace_batched(dm, wl.sza, wl.azimuth, counts, 23, brick=wl.brick, gpoint_diffuse=fd, timed=True)
+    ms = rt3d.last_trace_ms()
+    h, cols, sfc, per_col = check_direct_columns(rt3d, m, raw, total, wl.sza, wl.azimuth, seed=4)
+    ledger_ok(h, total)
+    say("two-stream entry: kernel ms", ms, "mean diffuse fraction", info["mean_diffuse_fraction"])
+    ref = direct_expectation(m, wl.sza, wl.azimuth, counts, cols, fd=fd.cpu().numpy())
+    got = np.array([sfc[j, i] for i, j in cols])
+    se = np.sqrt(np.maximum(ref * (1 - ref), 1e-4) / per_col)
+    say("two-stream entry direct columns: max |z|", float(np.max(np.abs(got - ref) / se)))
     assert np.all(np.abs(got - ref) <= 5 * se + 1e-3), np.c_[got, ref, se]

@@ -209,7 +209,7 @@ def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: in
     return losses, t_steps / max(step, 1)
 
 
-def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024),
+def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4096),
              low=(64, 128, 192, 256, 320, 384, 512, 768, 1024), tod_entry: bool = True):
     tr = Tracer(wl, tod_entry=tod_entry)
     g = tr.grid

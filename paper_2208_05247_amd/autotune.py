@@ -18,7 +18,7 @@ import dataclasses
 import hashlib
 import json
 import os
-from typing import Callable, Dict, List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 import torch

@@ -138,8 +138,8 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const ConvArgs a) {
 // halo is staged in LDS once (zero outside the domain); every wave then runs
 // the 27 taps over its 2 rows x 2 cout tiles: A fragments are contiguous
 // 1 KiB rows of the staged halo, B fragments (weights) come from global
-// memory, where the small weight tensor stays cache resident, and each is
-// used by two MFMAs.
+// memory, where the small weight tensor stays cache resident, one tap
+// ahead of their use, and each is used by two MFMAs.
 constexpr int kTY = 8, kTX = 32;
 constexpr int kHaloY = kTY + 2, kHaloX = kTX + 2;
 constexpr int kHaloVox = 3 * kHaloY * kHaloX;
@@ -170,6 +170,20 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[r][ct][e] = 0.0f;
 
+    // weight fragments of (chunk c, tap t) for this lane's output channels;
+    // the next tap's are loaded before the current tap's MFMAs run, so their
+    // latency hides behind them (branch-free: past the last chunk or channel
+    // tile the address is clamped in bounds and the fragment is never used)
+    auto load_b = [&](int c, int t, uint4* out) {
+        const int cc = min(c, cin - 16);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int co = min(co0 + 32 * ct + m, a.cout - 1);
+            out[ct] = *(const uint4*)(a.w + ((long)co * 27 + t) * cin + cc + 8 * half);
+        }
+    };
+    uint4 bv[2];
+    load_b(0, 0, bv);
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();  // the previous chunk's halo is no longer read
         for (int i = threadIdx.x; i < kHaloVox * 2; i += 256) {
@@ -191,17 +205,13 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
             tile[i] = val;
         }
         __syncthreads();
+#pragma unroll
         for (int t = 0; t < 27; ++t) {
             const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            uint4 bv[2];
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-                bv[ct] = make_uint4(0u, 0u, 0u, 0u);
-                if (ct < nct) {
-                    const int co = co0 + 32 * ct + m;
-                    bv[ct] = *(const uint4*)(a.w + ((long)co * 27 + t) * cin + c0 + 8 * half);
-                }
-            }
+            uint4 bn[2];
+            if (t < 26) load_b(c0, t + 1, bn);
+            else load_b(c0 + 16, 0, bn);
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const uint4 av = tile[((dz * kHaloY + row0 + r + dy) * kHaloX + m + dx) * 2 + half];
@@ -211,6 +221,8 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
                         acc[r][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[ct]),
                                                                              acc[r][ct], 0, 0, 0);
             }
+            bv[0] = bn[0];
+            bv[1] = bn[1];
         }
     }
 #pragma unroll

@@ -133,18 +133,20 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const ConvArgs a) {
 }
 
 // Tiled 3x3x3 convolution.  A workgroup (4 waves) owns an output tile of
-// kTY y-rows x kTX x-voxels at one z and a slab of up to 64 output channels.
-// For each 16-channel input chunk the (3 x (kTY+2) x (kTX+2))-voxel input
-// halo is staged in LDS once (zero outside the domain); every wave then runs
-// the 27 taps over its 2 rows x 2 cout tiles: A fragments are contiguous
-// 1 KiB rows of the staged halo, B fragments (weights) come from global
-// memory, where the small weight tensor stays cache resident, one tap
-// ahead of their use, and each is used by two MFMAs.
-constexpr int kTY = 8, kTX = 32;
+// kZ z-slices x kTY y-rows x kTX x-voxels and a slab of up to 64 output
+// channels.  For each 16-channel input chunk the
+// ((kZ+2) x (kTY+2) x (kTX+2))-voxel input halo is staged in LDS once (zero
+// outside the domain), so a staged plane serves kZ output planes; every
+// wave then runs the 27 taps over its 2 rows x 2 cout tiles in each output
+// plane: A fragments are contiguous 1 KiB rows of the staged halo, B
+// fragments (weights) come from global memory, where the small weight
+// tensor stays cache resident, one tap ahead of their use, and each is used
+// by 2 kZ MFMAs.
+constexpr int kTY = 8, kTX = 32, kZ = 2;
 constexpr int kHaloY = kTY + 2, kHaloX = kTX + 2;
-constexpr int kHaloVox = 3 * kHaloY * kHaloX;
+constexpr int kHaloVox = (kZ + 2) * kHaloY * kHaloX;
 
-__global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_tiled_kernel(const ConvArgs a) {
     __shared__ uint4 tile[kHaloVox * 2];  // 16 channels = two 16-byte halves per voxel
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, half = lane >> 5;
@@ -156,19 +158,21 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
     const int txi = (int)(b % tiles_x);
     b /= tiles_x;
     const int tyi = (int)(b % tiles_y);
-    const int zz = (int)(b / tiles_y);
+    const int z0 = (int)(b / tiles_y) * kZ;
     const int x0 = txi * kTX, y0 = tyi * kTY;
     const int co0 = slab * 64;
     const int nct = min(2, (a.cout - co0) / 32);
     const int cin = a.c1 + a.c2;
     const int row0 = 2 * wave;  // rows row0, row0 + 1 of the tile
-    f32x16 acc[2][2];
+    f32x16 acc[kZ][2][2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int oz = 0; oz < kZ; ++oz)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[r][ct][e] = 0.0f;
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[oz][r][ct][e] = 0.0f;
 
     // weight fragments of (chunk c, tap t) for this lane's output channels;
     // the next tap's are loaded before the current tap's MFMAs run, so their
@@ -189,7 +193,7 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
         for (int i = threadIdx.x; i < kHaloVox * 2; i += 256) {
             const int v = i >> 1, part = i & 1;
             const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY, hz = v / (kHaloX * kHaloY);
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
             uint4 val = make_uint4(0u, 0u, 0u, 0u);
             if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
                 const uint16_t* src;
@@ -213,39 +217,47 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
             else load_b(c0 + 16, 0, bn);
             __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const uint4 av = tile[((dz * kHaloY + row0 + r + dy) * kHaloX + m + dx) * 2 + half];
+            for (int oz = 0; oz < kZ; ++oz)
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
-                    if (ct < nct)
-                        acc[r][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[ct]),
-                                                                             acc[r][ct], 0, 0, 0);
-            }
+                for (int r = 0; r < 2; ++r) {
+                    // output plane oz reads staged plane oz + dz
+                    const uint4 av = tile[(((oz + dz) * kHaloY + row0 + r + dy) * kHaloX + m + dx) * 2 + half];
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        if (ct < nct)
+                            acc[oz][r][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                as_bf16x8(av), as_bf16x8(bv[ct]), acc[oz][r][ct], 0, 0, 0);
+                }
             bv[0] = bn[0];
             bv[1] = bn[1];
         }
     }
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int y = y0 + row0 + r;
-        if (y >= a.H) continue;
+    for (int oz = 0; oz < kZ; ++oz) {
+        const int zz = z0 + oz;
+        if (zz >= a.D) continue;
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-            if (ct >= nct) continue;
-            const int n = co0 + 32 * ct + m;
-            const float bias = a.bias ? a.bias[n] : 0.0f;
+        for (int r = 0; r < 2; ++r) {
+            const int y = y0 + row0 + r;
+            if (y >= a.H) continue;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
-                if (x >= a.W) continue;
-                float v = acc[r][ct][e] + bias;
-                if (a.relu) v = fmaxf(v, 0.0f);
-                const long vox = ((long)zz * a.H + y) * a.W + x;
-                if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
-                if (n < a.o1) {
-                    if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
-                } else if (a.y2) {
-                    a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+            for (int ct = 0; ct < 2; ++ct) {
+                if (ct >= nct) continue;
+                const int n = co0 + 32 * ct + m;
+                const float bias = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
+                    if (x >= a.W) continue;
+                    float v = acc[oz][r][ct][e] + bias;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    const long vox = ((long)zz * a.H + y) * a.W + x;
+                    if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
+                    if (n < a.o1) {
+                        if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
+                    } else if (a.y2) {
+                        a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+                    }
                 }
             }
         }
@@ -254,17 +266,20 @@ __global__ void __launch_bounds__(256) conv3_tiled_kernel(const ConvArgs a) {
 
 // 3x3x3 convolution with exactly 32 output channels (one MFMA column tile,
 // so an input fragment cannot be shared between output-channel tiles).
-// Instead each wave owns 4 output rows and, per z-slice of the kernel, keeps
-// its 9 weight fragments of the current 16-channel chunk in registers: it
-// walks the 6 staged input rows its outputs need, 3 x-shifts each, and feeds
-// every fragment it reads from LDS to all (up to 3) of its output rows that
-// use it.  Workgroup tile:
-// 16 rows x 32 voxels at one z.
+// Instead each wave owns 4 output rows in each of the workgroup's 2 output
+// z-slices and, per z-slice of the kernel, keeps its 9 weight fragments of
+// the current 16-channel chunk in registers: it walks the 6 staged input
+// rows its outputs need in both input planes that kernel slice reaches,
+// 3 x-shifts each, and feeds every fragment it reads from LDS to all (up
+// to 3) of its output rows that use it.  Workgroup tile: 2 z x 16 rows x
+// 32 voxels, so a staged input plane serves two output planes (4 planes
+// staged per 2 outputs instead of 3 per 1).
 constexpr int kTY32 = 16;
 constexpr int kHaloY32 = kTY32 + 2;
-constexpr int kHaloVox32 = 3 * kHaloY32 * kHaloX;
+constexpr int kZ32 = 2;
+constexpr int kHaloVox32 = (kZ32 + 2) * kHaloY32 * kHaloX;
 
-__global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_c32_kernel(const ConvArgs a) {
     __shared__ uint4 tile[kHaloVox32 * 2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, half = lane >> 5;
@@ -273,22 +288,24 @@ __global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
     const int txi = (int)(b % tiles_x);
     b /= tiles_x;
     const int tyi = (int)(b % tiles_y);
-    const int zz = (int)(b / tiles_y);
+    const int z0 = (int)(b / tiles_y) * kZ32;
     const int x0 = txi * kTX, y0 = tyi * kTY32;
     const int cin = a.c1 + a.c2;
     const int row0 = 4 * wave;
-    f32x16 acc[4];
+    f32x16 acc[kZ32][4];
 #pragma unroll
-    for (int o = 0; o < 4; ++o)
+    for (int oz = 0; oz < kZ32; ++oz)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[o][e] = 0.0f;
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[oz][o][e] = 0.0f;
 
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();
         for (int i = threadIdx.x; i < kHaloVox32 * 2; i += 256) {
             const int v = i >> 1, part = i & 1;
             const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
             uint4 val = make_uint4(0u, 0u, 0u, 0u);
             if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
                 const uint16_t* src;
@@ -311,16 +328,23 @@ __global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
             for (int t = 0; t < 9; ++t)
                 bv[t] = *(const uint4*)(a.w + ((long)m * 27 + dz * 9 + t) * cin + c0 + 8 * half);
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
+            for (int oz = 0; oz < kZ32; ++oz)
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const uint4 av = tile[((dz * kHaloY32 + row0 + r) * kHaloX + m + dx) * 2 + half];
+                for (int r = 0; r < 6; ++r) {
+                    // keeps the scheduler from hoisting every LDS read of the
+                    // slice ahead of the MFMAs (it would spill at 2 waves/SIMD)
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int o = 0; o < 4; ++o) {
-                        const int dy = r - o;  // output row o reads halo row o + dy
-                        if (dy >= 0 && dy <= 2)
-                            acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[dy * 3 + dx]),
-                                                                             acc[o], 0, 0, 0);
+                    for (int dx = 0; dx < 3; ++dx) {
+                        // output plane oz reads staged plane oz + dz
+                        const uint4 av = tile[(((oz + dz) * kHaloY32 + row0 + r) * kHaloX + m + dx) * 2 + half];
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) {
+                            const int dy = r - o;  // output row o reads halo row o + dy
+                            if (dy >= 0 && dy <= 2)
+                                acc[oz][o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    as_bf16x8(av), as_bf16x8(bv[dy * 3 + dx]), acc[oz][o], 0, 0, 0);
+                        }
                     }
                 }
         }
@@ -328,21 +352,26 @@ __global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
     const int n = m;
     const float bias = a.bias ? a.bias[n] : 0.0f;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const int y = y0 + row0 + o;
-        if (y >= a.H) continue;
+    for (int oz = 0; oz < kZ32; ++oz) {
+        const int zz = z0 + oz;
+        if (zz >= a.D) continue;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
-            if (x >= a.W) continue;
-            float v = acc[o][e] + bias;
-            if (a.relu) v = fmaxf(v, 0.0f);
-            const long vox = ((long)zz * a.H + y) * a.W + x;
-            if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
-            if (n < a.o1) {
-                if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
-            } else if (a.y2) {
-                a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+        for (int o = 0; o < 4; ++o) {
+            const int y = y0 + row0 + o;
+            if (y >= a.H) continue;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
+                if (x >= a.W) continue;
+                float v = acc[oz][o][e] + bias;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                const long vox = ((long)zz * a.H + y) * a.W + x;
+                if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
+                if (n < a.o1) {
+                    if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
+                } else if (a.y2) {
+                    a.y2[vox * (a.cout - a.o1) + (n - a.o1)] = f2bf(v);
+                }
             }
         }
     }
@@ -355,8 +384,10 @@ __global__ void __launch_bounds__(256) conv3_c32_kernel(const ConvArgs a) {
 // a row takes 9 MFMAs instead of 27 of 16 mostly-zero channels.  Tile and
 // reuse as in conv3_c32_kernel (16 rows x 32 voxels, 4 rows per wave, every
 // staged input row fed to all output rows that use it).
+constexpr int kHaloVoxC4 = 3 * kHaloY32 * kHaloX;
+
 __global__ void __launch_bounds__(256) conv3_c4_kernel(const ConvArgs a) {
-    __shared__ uint2 tile[kHaloVox32];
+    __shared__ uint2 tile[kHaloVoxC4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, half = lane >> 5;
     const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY32 - 1) / kTY32;
@@ -367,7 +398,7 @@ __global__ void __launch_bounds__(256) conv3_c4_kernel(const ConvArgs a) {
     const int zz = (int)(b / tiles_y);
     const int x0 = txi * kTX, y0 = tyi * kTY32;
     const int row0 = 4 * wave;
-    for (int v = threadIdx.x; v < kHaloVox32; v += 256) {
+    for (int v = threadIdx.x; v < kHaloVoxC4; v += 256) {
         const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
         const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
         uint2 val = make_uint2(0u, 0u);
@@ -736,11 +767,12 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
         if (tiles > 0x7fffffffL) return RT3D_EINVAL;
         hipLaunchKernelGGL(conv3_c4_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
     } else if (c->ksize == 3 && c->cout == 32) {
-        const long tiles = (long)c->D * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
+        const long tiles = (long)((c->D + kZ32 - 1) / kZ32) * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
         if (tiles > 0x7fffffffL) return RT3D_EINVAL;
         hipLaunchKernelGGL(conv3_c32_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
     } else if (c->ksize == 3) {
-        const long tiles = (long)c->D * ((c->H + kTY - 1) / kTY) * ((c->W + kTX - 1) / kTX) * ((c->cout + 63) / 64);
+        const long tiles =
+            (long)((c->D + kZ - 1) / kZ) * ((c->H + kTY - 1) / kTY) * ((c->W + kTX - 1) / kTX) * ((c->cout + 63) / 64);
         if (tiles > 0x7fffffffL) return RT3D_EINVAL;
         hipLaunchKernelGGL(conv3_tiled_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
     } else {

@@ -41,7 +41,8 @@ def rel(a, b):
     return float((a - b).norm() / max(b.norm(), 1e-30))
 
 
-@pytest.mark.parametrize("shape", [(3, 5, 37, 16, 32, 64, 3), (4, 4, 64, 32, 0, 32, 3), (2, 3, 20, 32, 0, 32, 1)])
+@pytest.mark.parametrize("shape", [(3, 5, 37, 16, 32, 64, 3), (4, 4, 64, 32, 0, 32, 3), (2, 3, 20, 32, 0, 32, 1),
+                                   (3, 18, 40, 32, 16, 32, 3), (5, 17, 33, 32, 0, 32, 3), (5, 11, 35, 32, 0, 64, 3)])
 def test_conv_forward_and_gradients(dn, shape):
     D, H, W, c1, c2, cout, k = shape
     g = torch.Generator().manual_seed(7)

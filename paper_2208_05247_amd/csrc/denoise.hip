@@ -146,6 +146,43 @@ constexpr int kTY = 8, kTX = 32, kZ = 2;
 constexpr int kHaloY = kTY + 2, kHaloX = kTX + 2;
 constexpr int kHaloVox = (kZ + 2) * kHaloY * kHaloX;
 
+// Stages the input halo of one 16-channel chunk, planes z0-1 .. z0+NZ and
+// rows y0-1 .. y0+HY-2 of columns x0-1 .. x0+kTX, into LDS as two 16-byte
+// halves per voxel (zero outside the domain), with NT threads.  Every load
+// address is clamped into the domain and the zero is selected afterwards,
+// so the loop is straight-line code and a batch of SB loads per thread is
+// in flight at once (a guarded load per iteration would wait for each).
+template <int NZ, int HY, int NT, int SB>
+__device__ __forceinline__ void stage_halo16(uint4* tile, const ConvArgs& a, int c0, int x0, int y0, int z0) {
+    constexpr int kSlots = NZ * HY * kHaloX * 2, kPer = (kSlots + NT - 1) / NT;
+    const bool from1 = c0 < a.c1;
+    const uint16_t* base = from1 ? a.x1 + c0 : a.x2 + (c0 - a.c1);
+    const long cs = from1 ? a.c1 : a.c2;
+    const bool half_res = from1 && a.up1;
+#pragma unroll 1
+    for (int j0 = 0; j0 < kPer; j0 += SB) {  // not unrolled: keeps the address math out of the chunk loop's registers
+        uint4 v[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+            const int i = threadIdx.x + NT * (j0 + j);
+            const int vx = i >> 1, part = i & 1;
+            const int hx = vx % kHaloX, hy = (vx / kHaloX) % HY, hz = vx / (kHaloX * HY);
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            const bool in = x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D;
+            const int xc = min(max(x, 0), a.W - 1), yc = min(max(y, 0), a.H - 1), zc = min(max(z, 0), a.D - 1);
+            const long vox = half_res ? ((long)(zc >> 1) * (a.H >> 1) + (yc >> 1)) * (a.W >> 1) + (xc >> 1)
+                                      : ((long)zc * a.H + yc) * a.W + xc;
+            const uint4 ld = *(const uint4*)(base + vox * cs + 8 * part);
+            v[j] = in ? ld : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+            const int i = threadIdx.x + NT * (j0 + j);
+            if (j0 + j < kPer && i < kSlots) tile[i] = v[j];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_tiled_kernel(const ConvArgs a) {
     __shared__ uint4 tile[kHaloVox * 2];  // 16 channels = two 16-byte halves per voxel
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -190,24 +227,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     load_b(0, 0, bv);
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();  // the previous chunk's halo is no longer read
-        for (int i = threadIdx.x; i < kHaloVox * 2; i += 256) {
-            const int v = i >> 1, part = i & 1;
-            const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY, hz = v / (kHaloX * kHaloY);
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
-            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
-                const uint16_t* src;
-                if (c0 < a.c1) {
-                    const long v1 = a.up1 ? ((long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)
-                                          : ((long)z * a.H + y) * a.W + x;
-                    src = a.x1 + v1 * a.c1 + c0;
-                } else {
-                    src = a.x2 + (((long)z * a.H + y) * a.W + x) * a.c2 + (c0 - a.c1);
-                }
-                val = *(const uint4*)(src + 8 * part);
-            }
-            tile[i] = val;
-        }
+        stage_halo16<kZ + 2, kHaloY, 256, 4>(tile, a, c0, x0, y0, z0);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
@@ -302,24 +322,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
 
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();
-        for (int i = threadIdx.x; i < kHaloVox32 * 2; i += 256) {
-            const int v = i >> 1, part = i & 1;
-            const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
-            if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D) {
-                const uint16_t* src;
-                if (c0 < a.c1) {
-                    const long v1 = a.up1 ? ((long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)
-                                          : ((long)z * a.H + y) * a.W + x;
-                    src = a.x1 + v1 * a.c1 + c0;
-                } else {
-                    src = a.x2 + (((long)z * a.H + y) * a.W + x) * a.c2 + (c0 - a.c1);
-                }
-                val = *(const uint4*)(src + 8 * part);
-            }
-            tile[i] = val;
-        }
+        stage_halo16<kZ32 + 2, kHaloY32, 256, 4>(tile, a, c0, x0, y0, z0);
         __syncthreads();
         for (int dz = 0; dz < 3; ++dz) {
             // the 9 weight fragments of this z-slice of the kernel

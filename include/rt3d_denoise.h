@@ -64,6 +64,19 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
                                const float* bias, int32_t relu, uint16_t* y1, uint16_t* y2, int32_t o1, float* yf,
                                void* stream);
 
+/* The network's last two layers in one launch (inference): a 3x3x3
+ * convolution to exactly 32 channels, y = act(conv(concat(x1, x2), w) +
+ * bias) rounded to BF16 (c1, c2 multiples of 16; up1 as above), followed by
+ * the 1x1x1 head hw [32][32] (output channel, input channel) with bias hb
+ * (may be NULL).  Only the FP32 head channels [0, hcols) are written, to
+ * hy [vox][hcols] (1 <= hcols <= 32); y itself is never stored.  The result
+ * is bitwise that of rt3d_dn_conv3d_fwd for the convolution followed by
+ * rt3d_dn_conv3d_fwd for the head (same products in the same order).
+ * RT3D_EINVAL on a NULL required pointer or an unsupported shape. */
+rt3d_status rt3d_dn_conv3d_fwd_head(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* w,
+                                    const float* bias, int32_t relu, const uint16_t* hw, const float* hb, int32_t hcols,
+                                    float* hy, void* stream);
+
 /* wt[ci][k^3 - 1 - t][co] = w[co][t][ci]: the kernel of the data gradient. */
 rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, int32_t cin, int32_t ksize,
                                  void* stream);

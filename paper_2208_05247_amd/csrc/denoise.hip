@@ -75,6 +75,12 @@ struct ConvArgs {
     int D, H, W, cout, relu;
     int up1;               // x1 at half resolution, read nearest-upsampled
     int yf_cols;
+    // optional 1x1x1 head fused after a 32-output 3x3x3 convolution:
+    // hy[vox][hcols] = FP32 channels [0, hcols) of conv1(bf16(y), hw) + hb
+    const uint16_t* hw;    // [32][32] (head output, input channel)
+    const float* hb;       // [32] or null
+    float* hy;
+    int hcols;
 };
 
 template <int KS>
@@ -298,6 +304,8 @@ constexpr int kTY32 = 16;
 constexpr int kHaloY32 = kTY32 + 2;
 constexpr int kZ32 = 2;
 constexpr int kHaloVox32 = (kZ32 + 2) * kHaloY32 * kHaloX;
+// the fused head reuses the halo tile: 4 waves x kZ32 x 4 rows x 32 x 32 BF16
+static_assert(4 * kZ32 * 4 * 32 * 32 * 2 <= kHaloVox32 * 2 * 16, "head scratch exceeds the halo tile");
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_c32_kernel(const ConvArgs a) {
     __shared__ uint4 tile[kHaloVox32 * 2];
@@ -354,6 +362,57 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     }
     const int n = m;
     const float bias = a.bias ? a.bias[n] : 0.0f;
+    if (a.hw) {
+        // Fused head.  Each wave writes its BF16 activations, 32 voxels x 32
+        // channels per output row, to its own part of the (no longer needed)
+        // halo tile, so that a lane can read the 8 consecutive channels of
+        // one voxel that the A operand takes; the head then runs the same
+        // two MFMAs per row as the 1x1x1 convolution kernel, in the same
+        // order, so its output is bitwise that of the unfused pair.
+        uint16_t* ht = reinterpret_cast<uint16_t*>(tile) + wave * (kZ32 * 4 * 32 * 32);
+        __syncthreads();  // every wave is done reading the halo
+#pragma unroll
+        for (int oz = 0; oz < kZ32; ++oz)
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float v = acc[oz][o][e] + bias;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    ht[((oz * 4 + o) * 32 + 8 * (e >> 2) + 4 * half + (e & 3)) * 32 + n] = f2bf(v);
+                }
+        __syncthreads();
+        uint4 hwv[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) hwv[c] = *(const uint4*)(a.hw + m * 32 + 16 * c + 8 * half);
+        const float hbias = a.hb ? a.hb[n] : 0.0f;
+#pragma unroll
+        for (int oz = 0; oz < kZ32; ++oz) {
+            const int zz = z0 + oz;
+            if (zz >= a.D) continue;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int y = y0 + row0 + o;
+                if (y >= a.H) continue;
+                f32x16 h;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) h[e] = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const uint4 av = *(const uint4*)(ht + ((oz * 4 + o) * 32 + m) * 32 + 16 * c + 8 * half);
+                    h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(hwv[c]), h, 0, 0, 0);
+                }
+                if (n >= a.hcols) continue;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int x = x0 + 8 * (e >> 2) + 4 * half + (e & 3);
+                    if (x >= a.W) continue;
+                    a.hy[(((long)zz * a.H + y) * a.W + x) * a.hcols + n] = h[e] + hbias;
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int oz = 0; oz < kZ32; ++oz) {
         const int zz = z0 + oz;
@@ -765,6 +824,7 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
     a.D = c->D; a.H = c->H; a.W = c->W; a.cout = c->cout; a.relu = relu ? 1 : 0;
     a.up1 = c->up1 ? 1 : 0;
     a.yf_cols = c->yf_cols ? c->yf_cols : c->cout;
+    a.hw = nullptr; a.hb = nullptr; a.hy = nullptr; a.hcols = 0;
     if (four) {
         const long tiles = (long)c->D * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
         if (tiles > 0x7fffffffL) return RT3D_EINVAL;
@@ -783,6 +843,28 @@ rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const 
         const unsigned blocks = (unsigned)((waves + 3) / 4);
         hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
     }
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_conv3d_fwd_head(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* w,
+                                    const float* bias, int32_t relu, const uint16_t* hw, const float* hb, int32_t hcols,
+                                    float* hy, void* stream) {
+    if (!c || !x1 || !w || (c->c2 > 0 && !x2) || !hw || !hy) return RT3D_EINVAL;
+    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->c1 <= 0 || c->c1 % 16 || c->c2 < 0 || c->c2 % 16)
+        return RT3D_EINVAL;
+    if (c->ksize != 3 || c->cout != 32 || hcols <= 0 || hcols > 32) return RT3D_EINVAL;
+    if (c->up1 && (c->D % 2 || c->H % 2 || c->W % 2)) return RT3D_EINVAL;
+    ConvArgs a;
+    a.x1 = x1; a.x2 = x2; a.c1 = c->c1; a.c2 = c->c2; a.w = w; a.bias = bias;
+    a.y1 = nullptr; a.y2 = nullptr; a.o1 = 32; a.yf = nullptr;
+    a.D = c->D; a.H = c->H; a.W = c->W; a.cout = 32; a.relu = relu ? 1 : 0;
+    a.up1 = c->up1 ? 1 : 0;
+    a.yf_cols = 32;
+    a.hw = hw; a.hb = hb; a.hy = hy; a.hcols = hcols;
+    const long tiles = (long)((c->D + kZ32 - 1) / kZ32) * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
+    if (tiles > 0x7fffffffL) return RT3D_EINVAL;
+    hipLaunchKernelGGL(conv3_c32_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a);
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }

@@ -54,6 +54,7 @@ def load():
     P, I, U = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
     sig = {
         "rt3d_dn_conv3d_fwd": [ctypes.POINTER(_Conv), P, P, P, P, I, P, P, I, P, P],
+        "rt3d_dn_conv3d_fwd_head": [ctypes.POINTER(_Conv), P, P, P, P, I, P, P, I, P, P],
         "rt3d_dn_flip_weights": [P, P, I, I, I, P],
         "rt3d_dn_conv3d_wgrad": [ctypes.POINTER(_Conv), P, P, P, P, P, P],
         "rt3d_dn_conv3d_wgrad_ws": [ctypes.POINTER(_Conv), P, P, P, P, P, P, ctypes.c_size_t, P],
@@ -78,7 +79,7 @@ def load():
     return lib
 
 
-EXPORTS = ("rt3d_dn_last_error", "rt3d_dn_conv3d_fwd", "rt3d_dn_flip_weights", "rt3d_dn_conv3d_wgrad",
+EXPORTS = ("rt3d_dn_last_error", "rt3d_dn_conv3d_fwd", "rt3d_dn_conv3d_fwd_head", "rt3d_dn_flip_weights", "rt3d_dn_conv3d_wgrad",
            "rt3d_dn_conv3d_wgrad_ws", "rt3d_dn_wgrad_workspace_size",
            "rt3d_dn_relu_bwd", "rt3d_dn_add", "rt3d_dn_pool2", "rt3d_dn_up2", "rt3d_dn_mse", "rt3d_dn_adam",
            "rt3d_dn_to_bf16", "rt3d_dn_features", "rt3d_dn_unfeature")
@@ -123,6 +124,23 @@ def conv_fwd(x1, x2, w, bias, relu, cout, ksize, y1=None, y2=None, o1=None, yf=N
     c = _Conv(D, H, W, c1, c2, cout, ksize, 1 if up1 else 0, int(yf_cols))
     _check(load().rt3d_dn_conv3d_fwd(ctypes.byref(c), _p(x1), _p(x2), _p(w), _p(bias), int(relu), _p(y1), _p(y2),
                                      int(o1), _p(yf), _s()), "rt3d_dn_conv3d_fwd")
+
+
+def conv_fwd_head(x1, x2, w, bias, relu, hw, hb, out, up1=False):
+    """A 3x3x3 convolution to 32 channels followed by the 1x1x1 head hw
+    [32][32] in one launch; out (FP32 [D][H][W][hcols]) receives the head's
+    first hcols channels, the 32-channel activation is not stored."""
+    D, H, W, c1 = x1.shape
+    if up1:
+        D, H, W = 2 * D, 2 * H, 2 * W
+    c2 = 0 if x2 is None else x2.shape[3]
+    if x2 is not None and tuple(x2.shape[:3]) != (D, H, W):
+        raise ValueError("x2 must be on the output grid")
+    if tuple(out.shape[:3]) != (D, H, W) or tuple(hw.shape[:1]) != (32,) or hw.numel() != 32 * 32:
+        raise ValueError("out must be on the output grid and hw [32][32]")
+    c = _Conv(D, H, W, c1, c2, 32, 3, 1 if up1 else 0, 0)
+    _check(load().rt3d_dn_conv3d_fwd_head(ctypes.byref(c), _p(x1), _p(x2), _p(w), _p(bias), int(relu), _p(hw),
+                                          _p(hb), int(out.shape[-1]), _p(out), _s()), "rt3d_dn_conv3d_fwd_head")
 
 
 def flip(w, cout, cin, ksize, out):
@@ -292,12 +310,16 @@ class Denoiser:
             # inference: the convolutions read the coarser level upsampled
             a["d2"] = self._conv("d2", a["b"], a["e2"], up1=True)
             a["d1"] = self._conv("d1", a["d2"], a["e1"], up1=True)
-            a["d0"] = self._conv("d0", a["d1"], a["e0"], up1=True)
-        # training needs every head channel (its gradient); inference only
-        # the NOUT used ones
-        nkeep = HEAD if keep else NOUT
-        out = torch.empty(D, H, W, nkeep, dtype=torch.float32, device=feat.device)
-        self._conv("head", a["d0"], yf=out, yf_cols=nkeep)
+            # the last convolution and the head in one launch (the 32-channel
+            # activation is never stored); only the NOUT used channels
+            out = torch.empty(D, H, W, NOUT, dtype=torch.float32, device=feat.device)
+            L = next(l for l in self.layers if l.name == "d0")
+            conv_fwd_head(a["d1"], a["e0"], self.pb["d0"], self.bias["d0"], L.relu, self.pb["head"],
+                          self.bias["head"], out, up1=True)
+            return out
+        # training needs every head channel (its gradient)
+        out = torch.empty(D, H, W, HEAD, dtype=torch.float32, device=feat.device)
+        self._conv("head", a["d0"], yf=out, yf_cols=HEAD)
         if keep:
             self.acts = a
         return out

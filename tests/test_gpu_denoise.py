@@ -210,6 +210,30 @@ def test_fused_upsampling_equals_materialised(dn, shape):
     assert torch.equal(got, ref)
 
 
+@pytest.mark.parametrize("shape", [(3, 18, 40, 32, 16, False, 2), (2, 9, 17, 32, 32, True, 2), (5, 16, 32, 16, 0, False, 32)])
+def test_fused_head_equals_separate_layers(dn, shape):
+    """The last 3x3x3 convolution (32 outputs, ReLU) and the 1x1x1 head in one
+    launch equal the two launches with the BF16 activation stored in
+    between, bit for bit; ragged tiles, odd depth, on-the-fly upsampling and
+    every head channel included."""
+    d, h, w, c1, c2, up, hcols = shape
+    D, H, W = (2 * d, 2 * h, 2 * w) if up else (d, h, w)
+    g = torch.Generator().manual_seed(29)
+    x1 = torch.randn(d, h, w, c1, generator=g).to(torch.bfloat16).cuda()
+    x2 = torch.randn(D, H, W, c2, generator=g).to(torch.bfloat16).cuda() if c2 else None
+    wt = (torch.randn(32, 27, c1 + c2, generator=g) * 0.1).to(torch.bfloat16).cuda()
+    bias = torch.randn(32, generator=g).cuda()
+    hw = (torch.randn(32, 1, 32, generator=g) * 0.2).to(torch.bfloat16).cuda()
+    hb = torch.randn(32, generator=g).cuda()
+    act = torch.empty(D, H, W, 32, dtype=torch.bfloat16, device="cuda")
+    dn.conv_fwd(x1, x2, wt, bias, True, 32, 3, y1=act, up1=up)
+    ref = torch.empty(D, H, W, hcols, dtype=torch.float32, device="cuda")
+    dn.conv_fwd(act, None, hw, hb, False, 32, 1, yf=ref, yf_cols=hcols)
+    got = torch.full((D, H, W, hcols), float("nan"), dtype=torch.float32, device="cuda")
+    dn.conv_fwd_head(x1, x2, wt, bias, True, hw, hb, got, up1=up)
+    assert torch.equal(got, ref)
+
+
 def test_inference_forward_equals_training_forward(dn):
     net = dn.Denoiser(base=32, seed=4)
     g = torch.Generator().manual_seed(2)

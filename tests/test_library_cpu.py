@@ -147,3 +147,28 @@ def test_denoiser_wgrad_workspace_checks(lib):
     assert f(ctypes.byref(good), fake, fake, fake, fake, None, fake, n - 1, None) == 1
     assert f(ctypes.byref(good), fake, fake, fake, fake, None, None, n, None) == 1
     assert f(ctypes.byref(good), fake, None, fake, fake, None, fake, n, None) == 1   # c2 > 0 needs x2
+
+
+def test_fused_head_argument_checks(lib):
+    """The fused convolution + head entry point rejects unsupported shapes and
+    missing pointers on the host, before any launch."""
+    from paper_2208_05247_amd import denoise as dn
+    dn.load()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the host checks reject first
+    f = lib.rt3d_dn_conv3d_fwd_head
+    good = dn._Conv(8, 8, 32, 32, 16, 32, 3, 0, 0)
+    assert f(ctypes.byref(good), fake, fake, fake, None, 1, None, None, 2, fake, None) == rt3d_einval()  # no head
+    assert f(ctypes.byref(good), fake, fake, fake, None, 1, fake, None, 2, None, None) == rt3d_einval()  # no output
+    assert f(ctypes.byref(good), fake, None, fake, None, 1, fake, None, 2, fake, None) == rt3d_einval()  # c2 needs x2
+    for hcols in (0, 33):
+        assert f(ctypes.byref(good), fake, fake, fake, None, 1, fake, None, hcols, fake, None) == rt3d_einval()
+    for bad in (dn._Conv(8, 8, 32, 32, 16, 64, 3, 0, 0),   # 64 outputs
+                dn._Conv(8, 8, 32, 32, 16, 32, 1, 0, 0),   # 1x1x1
+                dn._Conv(8, 8, 32, 4, 0, 32, 3, 0, 0),     # 4-channel first layer
+                dn._Conv(7, 8, 32, 32, 16, 32, 3, 1, 0)):  # odd grid with upsampling
+        assert f(ctypes.byref(bad), fake, fake, fake, None, 1, fake, None, 2, fake, None) == rt3d_einval()
+
+
+def rt3d_einval():
+    from paper_2208_05247_amd import rt3d
+    return rt3d.EINVAL

@@ -108,7 +108,9 @@ rt3d_status rt3d_dn_relu_bwd(const uint16_t* dy, const uint16_t* y, uint16_t* dz
 /* out = a + b elementwise (BF16). */
 rt3d_status rt3d_dn_add(const uint16_t* a, const uint16_t* b, uint16_t* out, uint64_t n, void* stream);
 
-/* 2x2x2 average pooling of x [D][H][W][C] into y [D/2][H/2][W/2][C]; with
+/* 2x2x2 average pooling of x [D][H][W][C] into y [D/2][H/2][W/2][C] (C a
+ * multiple of 8 and x, y 16-byte aligned; each output is the BF16 rounding
+ * of 1/8 of the FP32 sum of its 8 inputs taken in z, y, x order); with
  * backward != 0, x is the gradient at the pooled output and y receives the
  * gradient at the input (each input voxel gets 1/8 of its parent's). */
 rt3d_status rt3d_dn_pool2(const uint16_t* x, uint16_t* y, int32_t D, int32_t H, int32_t W, int32_t C,

@@ -41,6 +41,9 @@ rt3d_status dfail(hipError_t e, const char* where) {
         if (e_ != hipSuccess) return dfail(e_, #expr); \
     } while (0)
 
+// 16 zero bytes in global memory (read in place of voxels outside the domain)
+__device__ __align__(16) const uint32_t dn_zero16[4] = {0u, 0u, 0u, 0u};
+
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // FP32 -> BF16, round to nearest even (inputs are finite).
@@ -460,13 +463,32 @@ __global__ void __launch_bounds__(256) conv3_c4_kernel(const ConvArgs a) {
     const int zz = (int)(b / tiles_y);
     const int x0 = txi * kTX, y0 = tyi * kTY32;
     const int row0 = 4 * wave;
-    for (int v = threadIdx.x; v < kHaloVoxC4; v += 256) {
-        const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
-        const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
-        uint2 val = make_uint2(0u, 0u);
-        if (x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D)
-            val = *(const uint2*)(a.x1 + (((long)z * a.H + y) * a.W + x) * 4);
-        tile[v] = val;
+    {
+        // straight-line staging in batches of four loads per thread in
+        // flight
+        constexpr int kPer = (kHaloVoxC4 + 255) / 256, SB = 4;
+#pragma unroll 1
+        for (int j0 = 0; j0 < kPer; j0 += SB) {
+            uint2 vv[SB];
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int v = threadIdx.x + 256 * (j0 + j);
+                const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = zz + hz - 1;
+                const bool in = x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D;
+                const int xc = min(max(x, 0), a.W - 1), yc = min(max(y, 0), a.H - 1), zc = min(max(z, 0), a.D - 1);
+                // a voxel outside the domain reads zeros from dn_zero16: the
+                // address is selected, so the load cannot sink into a branch
+                // (which would wait for it before the next one is issued)
+                vv[j] = *(in ? (const uint2*)(a.x1 + (((long)zc * a.H + yc) * a.W + xc) * 4)
+                             : reinterpret_cast<const uint2*>(dn_zero16));
+            }
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int v = threadIdx.x + 256 * (j0 + j);
+                if (j0 + j < kPer && v < kHaloVoxC4) tile[v] = vv[j];
+            }
+        }
     }
     // B fragments of the 9 (z, y) tap pairs: lane half 0 holds taps dx = 0, 1,
     // half 1 tap dx = 2 and zeros
@@ -657,19 +679,34 @@ __global__ void add_kernel(const uint16_t* __restrict__ a, const uint16_t* __res
 }
 
 // 2x2x2 average pooling: out [D/2][H/2][W/2][C]
+// One thread per output voxel and 8-channel group: eight 16-byte loads, one
+// 16-byte store; every channel sums its 8 inputs in the same order.
 __global__ void pool2_kernel(const uint16_t* __restrict__ x, uint16_t* __restrict__ y, int D, int H, int W, int C) {
-    const int d = D / 2, h = H / 2, w = W / 2;
-    const size_t n = (size_t)d * h * w * C;
+    const int d = D / 2, h = H / 2, w = W / 2, cg = C / 8;
+    const size_t n = (size_t)d * h * w * cg;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        size_t v = i / C;
+        const int c8 = (int)(i % cg);
+        size_t v = i / cg;
         const int xo = (int)(v % w), yo = (int)((v / w) % h), zo = (int)(v / ((size_t)w * h));
-        float s = 0.0f;
+        float s[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] = 0.0f;
+#pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
-            s += bf2f(x[(((size_t)z * H + yy) * W + xx) * C + c]);
+            const uint4 u = *(const uint4*)(x + (((size_t)z * H + yy) * W + xx) * C + 8 * c8);
+            const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += bf2f((uint16_t)(wd[k] & 0xffffu));
+                s[2 * k + 1] += bf2f((uint16_t)(wd[k] >> 16));
+            }
         }
-        y[i] = f2bf(0.125f * s);
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = (uint32_t)f2bf(0.125f * s[2 * k]) | ((uint32_t)f2bf(0.125f * s[2 * k + 1]) << 16);
+        *(uint4*)(y + v * C + 8 * c8) = make_uint4(o[0], o[1], o[2], o[3]);
     }
 }
 
@@ -993,10 +1030,13 @@ rt3d_status rt3d_dn_pool2(const uint16_t* x, uint16_t* y, int32_t D, int32_t H, 
                           void* stream) {
     if (!x || !y || D <= 0 || H <= 0 || W <= 0 || C <= 0 || D % 2 || H % 2 || W % 2) return RT3D_EINVAL;
     const size_t n = (size_t)D * H * W * C;
-    if (backward)
+    if (backward) {
         hipLaunchKernelGGL(pool2_bwd_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
-    else
-        hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(n / 8)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
+    } else {
+        // 16-byte accesses: 8-channel groups, aligned tensors
+        if (C % 8 || ((uintptr_t)x | (uintptr_t)y) % 16) return RT3D_EINVAL;
+        hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for(n / 64)), dim3(256), 0, (hipStream_t)stream, x, y, D, H, W, C);
+    }
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }

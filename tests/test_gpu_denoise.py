@@ -98,6 +98,18 @@ def test_pool_and_upsample(dn):
     p = dn.pool2(xd).double().cpu()
     ref = F.avg_pool3d(x.permute(3, 0, 1, 2).unsqueeze(0), 2)[0].permute(1, 2, 3, 0)
     assert torch.allclose(p, bf(ref), atol=1e-2, rtol=1e-2)
+    # exactly: FP32 sum of the 8 inputs in z, y, x order, times 1/8, rounded to BF16
+    xf = x.float()
+    s = torch.zeros(2, 3, 4, 16)
+    for q in range(8):
+        s = s + xf[(q >> 2)::2, ((q >> 1) & 1)::2, (q & 1)::2]
+    assert torch.equal(p, (0.125 * s).to(torch.bfloat16).double())
+    for c in (8, 24, 40):  # other multiples of 8 channels
+        xc = torch.randn(2, 4, 6, c, generator=g).to(torch.bfloat16)
+        sc = torch.zeros(1, 2, 3, c)
+        for q in range(8):
+            sc = sc + xc.float()[(q >> 2)::2, ((q >> 1) & 1)::2, (q & 1)::2]
+        assert torch.equal(dn.pool2(xc.cuda()).cpu(), (0.125 * sc).to(torch.bfloat16))
     u = dn.up2(xd).double().cpu()
     assert torch.equal(u, dr.up(x.permute(3, 0, 1, 2).unsqueeze(0))[0].permute(1, 2, 3, 0))
     gu = dn.up2(dn.up2(xd), backward=True, out=torch.empty_like(xd)).double().cpu()

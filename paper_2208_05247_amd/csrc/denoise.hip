@@ -15,7 +15,8 @@
 // lane l, element r holds row 8*(r/4) + 4*(l/32) + r%4, column l%32.
 // 3x3x3 layers run from an input halo staged in LDS (conv3_tiled_kernel,
 // conv3_c32_kernel, conv3_c4_kernel); the 1x1x1 head uses conv_fwd_kernel,
-// one wave per 32 x 32 output tile with its operands read directly.
+// one wave per 32 x 32 output tile with its operands read directly, or in
+// inference runs inside conv3_c32_kernel after the last 3x3x3 layer.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -302,7 +303,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
 // 3 x-shifts each, and feeds every fragment it reads from LDS to all (up
 // to 3) of its output rows that use it.  Workgroup tile: 2 z x 16 rows x
 // 32 voxels, so a staged input plane serves two output planes (4 planes
-// staged per 2 outputs instead of 3 per 1).
+// staged per 2 outputs instead of 3 per 1).  With a head (ConvArgs::hw) the
+// 1x1x1 convolution follows in the epilogue and only its output is stored.
 constexpr int kTY32 = 16;
 constexpr int kHaloY32 = kTY32 + 2;
 constexpr int kZ32 = 2;

@@ -172,3 +172,17 @@ def test_fused_head_argument_checks(lib):
 def rt3d_einval():
     from paper_2208_05247_amd import rt3d
     return rt3d.EINVAL
+
+
+def test_pool_argument_checks(lib):
+    """The forward pooling takes 8-channel groups of 16-byte aligned tensors;
+    anything else is rejected on the host, before any launch."""
+    from paper_2208_05247_amd import denoise as dn
+    dn.load()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the host checks reject first
+    f = lib.rt3d_dn_pool2
+    assert f(fake, fake, 4, 4, 4, 12, 0, None) == rt3d_einval()                   # C not a multiple of 8
+    assert f(ctypes.c_void_p(264), fake, 4, 4, 4, 16, 0, None) == rt3d_einval()   # misaligned input
+    assert f(fake, ctypes.c_void_p(258), 4, 4, 4, 16, 0, None) == rt3d_einval()   # misaligned output
+    assert f(fake, fake, 3, 4, 4, 16, 0, None) == rt3d_einval()                   # odd grid
+    assert f(None, fake, 4, 4, 4, 16, 0, None) == rt3d_einval()

@@ -1,11 +1,17 @@
 """Throughput benchmark of the MI355X photon tracer.
 
-One step = one pass of the whole hot path over one batch of synthetic input:
-rt3d_trace (tally clearing, majorant build, persistent tracing kernel) and
-rt3d_finalize (normalisation) for 2^26 photons through the 256x256x128
-LES-shaped cumulus field (50 x 50 x 25 m cells, 200 Gaussian cloud blobs,
-SZA 45 deg, 8x8x8 acceleration-grid cells).  Inputs are resident in HBM
-before timing starts.  Prints one JSON line.
+Headline step = one pass of the whole hot path over the largest workload:
+1024 x 1024 x 128 cells of 25 x 25 x 20 m (cumulus field of ~800 Gaussian
+blobs), 112 shortwave g-points traced in ONE persistent launch
+(rt3d_trace_batched: tally clearing, packing, per-g-point majorants,
+tracing) and rt3d_finalize (heating rates), 2^30 photons split over the
+g-points in proportion to the two-stream flux entering the top of the
+domain (per-g-point diffuse fractions), sun at 60 deg zenith, surface
+albedo U[0.1, 0.3] per column.  Inputs are resident in HBM before timing
+starts.  Prints one JSON line; secondary legs (the 256x256x128 LES-shaped
+single g-point field, the 512x512x96 batched field, the memory-access
+ceiling, the two-stream column, denoiser inference, the time to a 5 %
+heating-rate error, the CPU oracle) are fields of the same line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -14,6 +20,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,10 +32,19 @@ sys.path.insert(0, ROOT)
 METRIC = "photon events/s + time to 5% heating-rate RMS, plain vs batched+denoised"
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
+HEADLINE = dict(seed=99_999, nx=1024, nz=128, dx=25.0, dz=20.0, sza=60.0, az=0.0, photons=1 << 30)
+HEADLINE_NAME = "batched_cumulus_1024x1024x128_112g"
+HEADLINE_BRICK = (8, 8, 8)
+TTR_REFERENCE_PER_COLUMN = 1 << 17
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
 
 # Algorithmic HBM bytes per event of the tracing kernel (random gathers and
-# tally read-modify-writes at the method's granularity; majorants live in
-# LDS/L1 and are not counted):
+# tally read-modify-writes at the method's granularity; majorants are not
+# counted):
 #   tentative collision: 8 B (k_ext, ssa) + 8 B heating-tally update
 #   real scattering:     + 4 B (k_ext_cloud); cloud scattering: + 4 B (g)
 #   surface hit:         4 B albedo + 8 B irradiance + 8 B absorbed tally
@@ -39,30 +55,7 @@ def algorithmic_bytes(stats) -> float:
             + 20.0 * s["surface"] + 8.0 * s["escape"])
 
 
-def measured_traffic(brick, photons):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on this exact kernel source and workload; else None."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_2208_05247_amd", "csrc", "rt3d.hip")
-    prof = os.path.join(ROOT, "profiles", "trace_kernel_les_cumulus_256x256x128.md")
-    if tuple(brick) != (8, 8, 8) or photons != 1 << 26 or not os.path.exists(prof):
-        return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    fields = {}
-    for line in open(prof):
-        if ":" in line and line.startswith("    "):
-            k, v = line.strip().split(":", 1)
-            fields[k.strip()] = v.strip()
-    if fields.get("source_sha256_16") != sha:
-        return None
-    return float(fields["traffic_bytes_per_launch"])
-
-
-TTR_SOURCES = ("paper_2208_05247_amd/csrc/rt3d.hip", "paper_2208_05247_amd/csrc/denoise.hip",
-               "paper_2208_05247_amd/denoise.py", "paper_2208_05247_amd/experiment.py")
-
-
-def sources_hash(paths) -> str:
+def source_hash(paths) -> str:
     import hashlib
     h = hashlib.sha256()
     for p in paths:
@@ -70,42 +63,134 @@ def sources_hash(paths) -> str:
     return h.hexdigest()[:16]
 
 
-def time_to_5pct():
-    """Plain vs batched+denoised time to a 5 % heating-rate RMS error, from
-    the committed summary of `python -m paper_2208_05247_amd.experiment`
-    (minutes of training and tracing, too long for the default bench run);
-    None unless it was measured with the current sources."""
-    prof = os.path.join(ROOT, "profiles", "time_to_5pct_batched_cumulus_1024x1024x128.md")
+TRACER_SOURCES = ("paper_2208_05247_amd/csrc/rt3d.hip",)
+
+
+def profile_fields(name: str) -> dict:
+    """Indented 'key: value' lines of a committed profile summary."""
+    prof = os.path.join(ROOT, "profiles", name)
+    fields = {}
     if not os.path.exists(prof):
-        return None
-    txt = open(prof).read()
-    if "    sources_sha256_16: " + sources_hash(TTR_SOURCES) not in txt or "```json" not in txt:
-        return None
-    return json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        return fields
+    for line in open(prof):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    return fields
 
 
-def cpu_baseline(wl, target_s: float = 20.0) -> dict:
-    import oracle
-    threads = min(16, os.cpu_count() or 1)
-    # probe twice (the first call also pays for converting the fields), then
-    # size the sample so that it takes about target_s
-    n = 1 << 19
-    for _ in range(2):
-        t0 = time.perf_counter()
-        oracle.trace(wl.fields, wl.sza, wl.azimuth, n, 123, brick=wl.brick, nthreads=threads)
-        dt = time.perf_counter() - t0
-    n2 = n
-    while n2 < wl.photons and dt * (n2 * 2) / n < target_s:
-        n2 *= 2
+def measured_traffic(profile: str, workload: str):
+    """HBM bytes per launch of the tracing kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE, each scaled by its
+    calibration factor), if it was taken on this exact kernel source and
+    workload; else None."""
+    f = profile_fields(profile)
+    if f.get("source_sha256_16") != source_hash(TRACER_SOURCES) or f.get("workload") != workload:
+        return None
+    try:
+        return float(f["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def headline_scene():
+    from paper_2208_05247_amd import experiment as ex
+    h = HEADLINE
+    return ex.scene(h["seed"], h["nx"], h["nx"], h["nz"], h["dx"], h["dz"], sza=h["sza"], az=h["az"],
+                    photons=h["photons"])
+
+
+def tracer_roofline(stats_tot: dict, launches: int, mean_kms: float, traffic) -> dict:
+    bytes_per_launch = algorithmic_bytes(stats_tot) / launches
+    achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBps": None if traffic is None else traffic / (mean_kms * 1e-3) / 1e9,
+            "traffic_frac": None if traffic is None else traffic / (mean_kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernel": "trace_kernel", "bytes_per_launch": bytes_per_launch}
+
+
+def headline(tr, counts, steps: int, warmup: int) -> dict:
+    """Batched launch + finalize on the largest workload, K timed steps."""
+    import torch
+    from paper_2208_05247_amd import rt3d
+    wl = tr.wl
+    total = int(counts.sum())
+
+    def step(seed):
+        raw = rt3d.trace_batched(tr.dm, wl.sza, wl.azimuth, counts, seed, brick=tr.brick, out=tr.out,
+                                 workspace=tr.ws, timed=True, gpoint_diffuse=tr.fd)
+        kms = rt3d.last_trace_ms()
+        rt3d.finalize(tr.grid, raw, total, layer_scale=tr.ls)
+        return kms, raw["stats"].clone()
+
+    for w in range(warmup):
+        step(1000 + w)
+    torch.cuda.synchronize()
+    kms, stats = [], []
     t0 = time.perf_counter()
-    r = oracle.trace(wl.fields, wl.sza, wl.azimuth, n2, 123, brick=wl.brick, nthreads=threads)
-    dt = time.perf_counter() - t0
-    st = dict(zip(oracle.STATS, r["stats"].tolist()))
-    ev = st["collisions"] + st["surface"]
-    return {"value": ev / dt, "unit": "photon events/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n2} photons of the same 256x256x128 cumulus workload (FP64 C oracle, "
-                      f"{threads} threads, {dt:.1f} s, {ev / n2:.1f} events/photon)",
-            "photons_per_s": n2 / dt}
+    for k in range(steps):
+        a, b = step(k + 1)
+        kms.append(a)
+        stats.append(b)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = {n: 0 for n in rt3d.STATS}
+    for st in stats:
+        for n, v in zip(rt3d.STATS, st.cpu().tolist()):
+            tot[n] += v
+    return {"wall": wall, "kernel_ms": kms, "stats": tot}
+
+
+def les_measurement(steps: int) -> dict:
+    """The 256x256x128 LES-shaped single g-point field (2^26 photons, 8^3
+    bricks, SZA 45 deg): trace + finalize per step."""
+    import torch
+    from paper_2208_05247_amd import rt3d
+    from paper_2208_05247_amd import synthetic as syn
+    wl = syn.les_cumulus()
+    grid = wl.fields.grid
+    df = rt3d.DeviceFields.from_host(wl.fields, "cuda")
+    out = rt3d.alloc_tallies(grid)
+    ws = rt3d.alloc_workspace(rt3d.workspace_size(grid, rt3d.options(brick=wl.brick)))
+
+    def step(seed):
+        raw = rt3d.trace(df, wl.sza, wl.azimuth, wl.photons, seed, brick=wl.brick, out=out, workspace=ws, timed=True)
+        kms = rt3d.last_trace_ms()
+        rt3d.finalize(grid, raw, wl.photons)
+        return kms, raw["stats"].clone()
+
+    step(999)
+    torch.cuda.synchronize()
+    kms, stats = [], []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        a, b = step(k + 1)
+        kms.append(a)
+        stats.append(b)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = {n: 0 for n in rt3d.STATS}
+    for st in stats:
+        for n, v in zip(rt3d.STATS, st.cpu().tolist()):
+            tot[n] += v
+    ev = tot["collisions"] + tot["surface"]
+    mean_kms = sum(kms) / len(kms)
+    traffic = measured_traffic("trace_kernel_les_cumulus_256x256x128.md", wl.name)
+    return {"workload": wl.name, "grid": [grid.nx, grid.ny, grid.nz], "photons": wl.photons,
+            "brick": list(wl.brick), "photon_events_per_s": ev / wall, "photons_per_s": tot["photons"] / wall,
+            "events_per_photon": ev / tot["photons"], "ms_per_step": wall * 1e3 / steps, "trace_kernel_ms": mean_kms,
+            "roofline": tracer_roofline(tot, steps, mean_kms, traffic)}
 
 
 def batched_measurement(steps: int) -> dict:
@@ -137,12 +222,9 @@ def batched_measurement(steps: int) -> dict:
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     # the paper's way: every g-point traced independently, one launch each
-    singles = [syn.BatchedMedium(m.grid, m.k_gas[n:n + 1], m.ssa_gas[n:n + 1], m.k_cloud, m.ssa_cloud,
-                                 m.g_cloud, m.albedo, m.weights[n:n + 1]) for n in range(m.n_gpoints)]
     dsingles = [rt3d.DeviceBatchedMedium(m.grid, dm.k_gas[n:n + 1].contiguous(), dm.ssa_gas[n:n + 1].contiguous(),
                                          dm.k_cloud, dm.ssa_cloud, dm.g_cloud, dm.albedo)
                 for n in range(m.n_gpoints)]
-    del singles
     ws1 = rt3d.alloc_workspace(rt3d.workspace_size_batched(m.grid, 1, opt))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,50 +240,6 @@ def batched_measurement(steps: int) -> dict:
             "trace_kernel_ms": sum(kms) / len(kms), "photon_events_per_s": evs / (wall * steps),
             "photons_per_s": total / wall, "separate_launches_ms": sep * 1e3,
             "speedup_vs_separate_launches": sep / wall}
-
-
-def entry_measurement(reps: int = 4) -> dict:
-    """Scrambled-Sobol against independent entry positions at equal photon
-    counts on the benchmark field: relative RMS error (the reference's own
-    noise removed, reference = two independent halves of 1024 photons per
-    column each) of the direct and diffuse surface irradiance and of the
-    absorbed power per cell, at 16, 64 and 256 photons per column (RMS of
-    `reps` seeds)."""
-    import torch
-    from paper_2208_05247_amd import rt3d
-    from paper_2208_05247_amd import synthetic as syn
-    from paper_2208_05247_amd.experiment import eps_against
-
-    wl = syn.les_cumulus()
-    grid = wl.fields.grid
-    df = rt3d.DeviceFields.from_host(wl.fields)
-    out = rt3d.alloc_tallies(grid)
-    ws = rt3d.alloc_workspace(rt3d.workspace_size(grid, rt3d.options(brick=wl.brick)))
-
-    def run(photons, seed, sob):
-        raw = rt3d.trace(df, wl.sza, wl.azimuth, photons, seed, brick=wl.brick, out=out, workspace=ws,
-                         sobol_entry=sob)
-        fin = rt3d.finalize(grid, raw, photons)
-        return {"sfc_dir": fin["sfc_dir"].double(), "sfc_dif": fin["sfc_dif"].double(),
-                "absorbed": (fin["abs_dir"].double() + fin["abs_dif"].double())}
-
-    ncol = grid.nx * grid.ny
-    ref_a = run(1024 * ncol, 90001, False)
-    ref_b = run(1024 * ncol, 90002, False)
-    res = {"workload": "les_cumulus_256x256x128", "reference_photons_per_column": 2048, "seeds": reps}
-    for per in (16, 64, 256):
-        row = {}
-        for sob in (False, True):
-            acc = {k: 0.0 for k in ref_a}
-            for r in range(reps):
-                h = run(per * ncol, 1000 * per + r, sob)
-                for k in acc:
-                    acc[k] += eps_against(h[k], ref_a[k], ref_b[k]) ** 2 / reps
-            row["sobol" if sob else "independent"] = {k: v ** 0.5 for k, v in acc.items()}
-        row["error_ratio"] = {k: row["sobol"][k] / row["independent"][k] for k in ref_a}
-        res[str(per)] = row
-    torch.cuda.synchronize()
-    return res
 
 
 def two_stream_measurement(reps: int = 20) -> dict:
@@ -229,6 +267,17 @@ def two_stream_measurement(reps: int = 20) -> dict:
             "diffuse_fraction_range": [float(fd.min()), float(fd.max())]}
 
 
+def denoiser_flops(net, D, H, W) -> float:
+    from paper_2208_05247_amd import denoise as dn
+    flops = 0.0
+    for L in net.layers:
+        level = {"e0": 0, "e1": 1, "e2": 2, "b": 3, "d2": 2, "d1": 1, "d0": 0, "head": 0}[L.name]
+        cin = 4 if L.name == "e0" else L.c1 + L.c2
+        cout = dn.NOUT if L.name == "head" else L.cout
+        flops += 2.0 * L.ksize ** 3 * cin * cout * (D * H * W) / 8 ** level
+    return flops
+
+
 def denoiser_measurement(reps: int = 3) -> dict:
     """Inference time of the denoiser on the 1024x1024x128 evaluation grid
     (random weights; time does not depend on them) and its MFMA roofline:
@@ -244,12 +293,7 @@ def denoiser_measurement(reps: int = 3) -> dict:
     hd = torch.rand(D, H, W, device="cuda", generator=g)
     hf = torch.rand(D, H, W, device="cuda", generator=g)
     ke = torch.rand(D, H, W, device="cuda", generator=g) * 0.01
-    flops = 0.0
-    for L in net.layers:
-        level = {"e0": 0, "e1": 1, "e2": 2, "b": 3, "d2": 2, "d1": 1, "d0": 0, "head": 0}[L.name]
-        cin = 4 if L.name == "e0" else L.c1 + L.c2
-        cout = dn.NOUT if L.name == "head" else L.cout
-        flops += 2.0 * L.ksize ** 3 * cin * cout * (D * H * W) / 8 ** level
+    flops = denoiser_flops(net, D, H, W)
     dn.denoise(net, hd, hf, ke, 0.1 * ke, 20.0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -265,45 +309,103 @@ def denoiser_measurement(reps: int = 3) -> dict:
                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "flops_per_call": flops}}
 
 
-# Merged tally atomics per tentative collision of the tracer on the benchmark
-# field: 31.2 per photon against 44.4 tentative collisions (0.70 ~ 11/16).
-ACCESS_ATOMICS_PER_16 = 11
-
-
-def access_ceiling(ncell: int, collisions_per_launch: float, kernel_ms=None, reps: int = 2) -> dict:
-    """What the memory system delivers for the tracer's access pattern on
-    the benchmark's footprint (ncell 16-byte records, 2 x ncell uint64
-    tallies): rt3d_access_probe with as many dependent random gathers as the
-    tracer makes tentative collisions per launch, 11 of 16 followed by a
-    random 64-bit atomic add, and once without the atomics; the tracer's
-    collision rate as a fraction of that ceiling (when kernel_ms is given)."""
+def access_ceiling(ncell: int, collisions_per_launch: float, atomics_per_16: int, kernel_ms=None,
+                   chains=(1, 2, 4)) -> dict:
+    """What the memory system delivers for the tracer's access pattern on a
+    footprint of ncell 16-byte records and 2 x ncell uint64 tallies
+    (rt3d_probe_gathers): as many dependent random gathers as the tracer
+    makes tentative collisions per launch, atomics_per_16 of every 16
+    followed by a random 64-bit atomic add, with 1, 2 and 4 independent
+    chains per lane; and once without the atomics.  The tracer's collision
+    rate as a fraction of the one-chain ceiling (when kernel_ms is given)."""
     import torch
-    from paper_2208_05247_amd import rt3d
+    from paper_2208_05247_amd import probe
     g = torch.Generator(device="cuda").manual_seed(3)
     rec = torch.rand((ncell, 4), generator=g, device="cuda", dtype=torch.float32)
     tally = torch.zeros(2 * ncell, dtype=torch.int64, device="cuda")
-    lanes = int(rt3d.load().rt3d_access_probe_lanes(0))
-    events = max(1, int(round(collisions_per_launch / lanes)))
-    rt3d.access_probe(rec, tally, 64, ACCESS_ATOMICS_PER_16, seed=1)
+    lanes = probe.lanes(0)
+    probe.gathers(rec, tally, 16, 1, atomics_per_16, seed=1)
     torch.cuda.synchronize()
     rates = {}
-    for name, a16 in (("with_atomics", ACCESS_ATOMICS_PER_16), ("gathers_only", 0)):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for r in range(reps):
-            rt3d.access_probe(rec, tally, events, a16, seed=r + 2)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        rates[name] = (ms, lanes * events / (ms * 1e-3))
-    res = {"lanes": lanes, "gathers_per_lane": events, "atomics_per_16": ACCESS_ATOMICS_PER_16,
-           "records_bytes": ncell * 16, "tally_bytes": 2 * ncell * 8,
-           "probe_ms": rates["with_atomics"][0], "ceiling_gathers_per_s": rates["with_atomics"][1],
-           "gathers_only_per_s": rates["gathers_only"][1]}
+    for a16 in (atomics_per_16, 0):
+        for c in chains:
+            events = max(1, int(round(collisions_per_launch / lanes / c)))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            probe.gathers(rec, tally, events, c, a16, seed=2 + c)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rates[f"{'with_atomics' if a16 else 'gathers_only'}_chains{c}"] = \
+                {"ms": ms, "gathers_per_s": lanes * events * c / (ms * 1e-3)}
+    del rec, tally
+    torch.cuda.empty_cache()
+    res = {"lanes": lanes, "atomics_per_16": atomics_per_16, "records_bytes": ncell * 16,
+           "tally_bytes": 2 * ncell * 8, "rates": rates}
     if kernel_ms:
         tracer = collisions_per_launch / (kernel_ms * 1e-3)
-        res.update({"tracer_collisions_per_s": tracer, "frac_of_ceiling": tracer / rates["with_atomics"][1]})
+        ceil1 = rates[f"with_atomics_chains1"]["gathers_per_s"]
+        res.update({"tracer_collisions_per_s": tracer, "frac_of_one_chain_ceiling": tracer / ceil1})
     return res
+
+
+def time_to_5pct(tr, ref_per_col: int) -> dict:
+    """Plain vs batched+denoised time to a 5 % heating-rate RMS error on the
+    headline scene, run here: the committed denoiser weights (trained by
+    `python -m paper_2208_05247_amd.experiment`, sha256-checked), a
+    reference of ref_per_col photons per column (two independent halves,
+    its own noise variance removed), the plain convergence sweep and the
+    denoised sweep (experiment.evaluate)."""
+    from paper_2208_05247_amd import experiment as ex
+    net, info = ex.load_committed_denoiser()
+    t0 = time.perf_counter()
+    res = ex.evaluate(net, tr.wl, ref_per_col, tracer=tr)
+    res["evaluation_wall_s"] = time.perf_counter() - t0
+    res["weights"] = info
+    return res
+
+
+def cpu_baseline(tr, counts, gpu_events_per_photon: float, target_s: float = 20.0) -> dict:
+    """The FP64 C oracle on a bounded sample of the headline workload, on
+    every host core: photons of a few g-points drawn with probability
+    proportional to their photon shares (each g-point traced on its full
+    1024x1024x128 fields with its own diffuse fraction), sized to about
+    target_s of CPU time."""
+    import oracle
+    threads = os.cpu_count() or 1
+    m = tr.m
+    rng = np.random.default_rng(12345)
+    shares = counts.astype(np.float64) / counts.sum()
+    picks = sorted(set(int(x) for x in rng.choice(m.n_gpoints, size=3, replace=False, p=shares)))
+    fdh = tr.fd.cpu().numpy() if tr.fd is not None else np.zeros(m.n_gpoints, np.float32)
+    fields = {n: m.fields_of(n) for n in picks}
+    # probe: a small run per g-point, then scale to the time target
+    n0 = 1 << 16
+    t_probe = 0.0
+    for n in picks:
+        t = time.perf_counter()
+        oracle.trace(fields[n], tr.wl.sza, tr.wl.azimuth, n0, 5 + n, brick=tr.brick,
+                     diffuse_fraction=float(fdh[n]), nthreads=threads)
+        t_probe += time.perf_counter() - t
+    per = n0
+    while per < (1 << 24) and t_probe * (2 * per) / n0 < target_s:
+        per *= 2
+    ev, ph, dt = 0, 0, 0.0
+    for n in picks:
+        t = time.perf_counter()
+        r = oracle.trace(fields[n], tr.wl.sza, tr.wl.azimuth, per, 77 + n, brick=tr.brick,
+                         diffuse_fraction=float(fdh[n]), nthreads=threads)
+        dt += time.perf_counter() - t
+        st = dict(zip(oracle.STATS, r["stats"].tolist()))
+        ev += st["collisions"] + st["surface"]
+        ph += per
+    return {"value": ev / dt, "unit": "photon events/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "sample": f"{per} photons in each of g-points {picks} of the {HEADLINE_NAME} workload (drawn by photon "
+                      f"share; full fields, two-stream diffuse fractions; FP64 C oracle, {threads} threads, "
+                      f"{dt:.1f} s, {ev / ph:.1f} events/photon against {gpu_events_per_photon:.1f} for the "
+                      f"GPU's whole g-point mix)",
+            "photons_per_s": ph / dt}
 
 
 def main():
@@ -311,22 +413,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--photons", type=int, default=1 << 26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--lds-majorant", type=int, default=0)
-    ap.add_argument("--no-merge", action="store_true", help="one tally atomic per deposit")
-    ap.add_argument("--sobol-entry", action="store_true", help="scrambled Sobol entry positions")
-    ap.add_argument("--refill-lanes", type=int, default=0, help="idle lanes before a wave refills (0 = 16)")
-    ap.add_argument("--max-walk", type=int, default=0, help="brick crossings per loop iteration (0 = automatic)")
+    ap.add_argument("--no-secondary", action="store_true", help="only the headline (and cpu baseline)")
+    ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-5 %% evaluation")
+    ap.add_argument("--ttr-reference", type=int, default=TTR_REFERENCE_PER_COLUMN,
+                    help="photons per column of the time-to-5 %% reference")
+    ap.add_argument("--brick", type=int, default=0, help="cubic brick edge of the headline (0 = default)")
     ap.add_argument("--inference-only", action="store_true",
                     help="only time denoiser inference on the 1024x1024x128 grid (prints its JSON)")
-    ap.add_argument("--access-probe", action="store_true",
-                    help="only run the memory-access ceiling probe on the benchmark's footprint (prints its JSON)")
-    ap.add_argument("--brick", type=int, default=8)
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched g-point measurement")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="only run the memory-access ceiling probe on the headline footprint (prints its JSON)")
+    ap.add_argument("--les-only", action="store_true", help="only the 256x256x128 single g-point leg")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run one plain device copy of this many bytes (for HBM counter scaling)")
+    ap.add_argument("--calibrate-gathers", type=int, default=0,
+                    help="only run the probe's random 16-byte gathers (no atomics) on this many bytes of "
+                         "records: one gather per 128-byte line, then the same with the line's other half "
+                         "gathered too (for the counters' fetch granularity)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the tracer is single-GPU (photons or g-points would be "
+              "sharded across GPUs with one all-reduce of the tallies; not built here)", file=sys.stderr)
+        sys.exit(2)
     if args.calibrate_copy:
         import torch
         a = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
@@ -336,99 +444,97 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.calibrate_copy}), flush=True)
         return
+    if args.calibrate_gathers:
+        import torch
+        from paper_2208_05247_amd import probe
+        n = args.calibrate_gathers // 16 // 8 * 8
+        rec = torch.ones((n, 4), dtype=torch.float32, device="cuda")
+        tally = torch.zeros(8, dtype=torch.int64, device="cuda")
+        res = {"records_bytes": n * 16, "lanes": probe.lanes(0), "events": 64}
+        for pair in (False, True):
+            probe.gathers(rec, tally, 64, 1, 0, line_pair=pair, seed=3)
+            torch.cuda.synchronize()
+        res["gathers_per_call"] = probe.lanes(0) * 64
+        print(json.dumps(res), flush=True)
+        return
     if args.inference_only:
         print(json.dumps({"denoiser_inference": denoiser_measurement()}), flush=True)
         return
-    if args.access_probe:
-        # the benchmark launch's 2^26 photons x 44.4 events, its 256x256x128 cells
-        print(json.dumps({"access_ceiling": access_ceiling(256 * 256 * 128, 44.4 * (1 << 26))}), flush=True)
+    if args.les_only:
+        print(json.dumps({"les": les_measurement(max(1, args.steps))}), flush=True)
         return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the tracer is single-GPU (photons or g-points would be "
-              "sharded across GPUs with one all-reduce of the tallies; not built here)", file=sys.stderr)
-        sys.exit(2)
 
     import torch
+    from paper_2208_05247_amd import experiment as ex
     from paper_2208_05247_amd import rt3d
-    from paper_2208_05247_amd import synthetic as syn
 
-    wl = syn.les_cumulus(photons=args.photons, brick=(args.brick,) * 3)
-    grid = wl.fields.grid
-    df = rt3d.DeviceFields.from_host(wl.fields, "cuda")
-    out = rt3d.alloc_tallies(grid)
-    opt = rt3d.options(brick=wl.brick)
-    ws = rt3d.alloc_workspace(rt3d.workspace_size(grid, opt))
-
-    def step(seed):
-        raw = rt3d.trace(df, wl.sza, wl.azimuth, wl.photons, seed, brick=wl.brick, out=out, workspace=ws,
-                         timed=True, lds_majorant=args.lds_majorant, merge=not args.no_merge,
-                         sobol_entry=args.sobol_entry, refill_lanes=args.refill_lanes, max_walk=args.max_walk)
-        kms = rt3d.last_trace_ms()
-        fin = rt3d.finalize(grid, raw, wl.photons)
-        return kms, raw["stats"].clone(), fin
-
-    for w in range(args.warmup):
-        step(1000 + w)
-    torch.cuda.synchronize()
-    kernel_ms, stats = [], []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        kms, st, _ = step(k + 1)
-        kernel_ms.append(kms)
-        stats.append(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    tot = {n: 0 for n in rt3d.STATS}
-    for st in stats:
-        for n, v in zip(rt3d.STATS, st.cpu().tolist()):
-            tot[n] += v
+    log("headline scene ...")
+    wl = headline_scene()
+    brick = (args.brick,) * 3 if args.brick else HEADLINE_BRICK
+    tr = ex.Tracer(wl, brick=brick)
+    counts = ex.multinomial_counts(tr.shares, HEADLINE["photons"], 5)
+    if args.probe_only:
+        print(json.dumps({"access_ceiling": access_ceiling(tr.grid.ncell, 5.0e10, 11)}), flush=True)
+        return
+    log("headline steps ...")
+    hl = headline(tr, counts, args.steps, args.warmup)
+    tot = hl["stats"]
     events = tot["collisions"] + tot["surface"]
-    ms_per_step = wall * 1e3 / args.steps
-    mean_kms = sum(kernel_ms) / len(kernel_ms)
-    bytes_per_launch = algorithmic_bytes(tot) / args.steps
-    achieved = bytes_per_launch / (mean_kms * 1e-3) / 1e9
-    traffic = measured_traffic(wl.brick, wl.photons) \
-        if (args.lds_majorant, args.no_merge, args.sobol_entry, args.refill_lanes, args.max_walk) == (0, False, False, 0, 0) \
-        else None
+    mean_kms = sum(hl["kernel_ms"]) / len(hl["kernel_ms"])
+    traffic = measured_traffic("trace_kernel_batched_cumulus_1024x1024x128.md", HEADLINE_NAME) \
+        if brick == HEADLINE_BRICK else None
+    g = tr.grid
     res = {
         "metric": METRIC,
-        "value": events / wall,
+        "value": events / hl["wall"],
         "unit": "photon events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": hl["wall"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "grid": [grid.nx, grid.ny, grid.nz],
-                   "cell_m": [grid.dx, grid.dy, grid.dz], "photons_per_step": wl.photons,
-                   "photons_per_column": wl.photons // grid.ncol, "sza_deg": wl.sza,
-                   "brick": list(wl.brick), "parallelism": "single GPU"},
-        "photons_per_s": tot["photons"] / wall,
+        "config": {"workload": HEADLINE_NAME, "grid": [g.nx, g.ny, g.nz], "cell_m": [g.dx, g.dy, g.dz],
+                   "g_points": int(tr.m.n_gpoints), "photons_per_step": int(counts.sum()),
+                   "photons_per_column": int(counts.sum()) // g.ncol, "sza_deg": wl.sza,
+                   "albedo": "U[0.1, 0.3] per column", "entry": "two-stream flux at the domain top",
+                   "brick": list(brick), "parallelism": "single GPU"},
+        "photons_per_s": tot["photons"] / hl["wall"],
         "events_per_photon": events / max(1, tot["photons"]),
         "trace_kernel_ms": mean_kms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_GBps": None if traffic is None else traffic / (mean_kms * 1e-3) / 1e9,
-                     "kernel": "trace_kernel",
-                     "bytes_per_launch": bytes_per_launch},
+        "roofline": tracer_roofline(tot, args.steps, mean_kms, traffic),
         "paper_context": "A100 40GiB: ~1.9e8 photons/s derived from 90 s for 112 g-points x 256 "
                          "photons/column on 768x768 columns (different fields)",
     }
-    if not args.no_batched:
-        res["access_ceiling"] = access_ceiling(grid.ncell, tot["collisions"] / args.steps, mean_kms)
-        res["batched"] = batched_measurement(max(1, min(args.steps, 3)))
-        res["sobol_entry"] = entry_measurement()
+    log(f"headline: {res['value']:.3e} events/s, kernel {mean_kms:.1f} ms")
+    if not args.no_secondary:
+        log("access ceiling ...")
+        merged = float(np.clip(ACCESS_ATOMICS_PER_16, 0, 16))
+        res["access_ceiling"] = access_ceiling(g.ncell, tot["collisions"] / args.steps, int(merged), mean_kms)
+    if not args.no_ttr:
+        log("time to 5 % ...")
+        res["time_to_5pct_heating_rms"] = time_to_5pct(tr, args.ttr_reference)
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        res["cpu_baseline"] = cpu_baseline(tr, counts, res["events_per_photon"])
+    del tr
+    torch.cuda.empty_cache()
+    if not args.no_secondary:
+        log("secondary legs ...")
+        res["les"] = les_measurement(max(1, min(args.steps, 5)))
+        res["batched_512x512x96"] = batched_measurement(max(1, min(args.steps, 3)))
         res["two_stream_tod"] = two_stream_measurement()
         res["denoiser_inference"] = denoiser_measurement()
-    res["time_to_5pct_heating_rms"] = time_to_5pct()
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(res), flush=True)
+
+
+# Tally atomics per 16 tentative collisions in the access probe: the merged
+# deposits per tentative collision of the tracer (31.2 per 44.4 on the
+# 256x256x128 field, ~11/16).
+ACCESS_ATOMICS_PER_16 = 11
 
 
 if __name__ == "__main__":

@@ -209,7 +209,9 @@ typedef struct {
                                 loop iteration before the wave re-converges;
                                 0 = automatic (3 with LDS majorants, else 2) */
     int32_t pool_photons;    /* photon ids a wave takes from the work queue
-                                at a time, 0 = 256 */
+                                at a time, 0 = 256, else >= 64 (one grab
+                                must cover every lane of a wave);
+                                1..63 and negative values: RT3D_EINVAL */
     int32_t refill_lanes;    /* a wave starts new photons once at least this
                                 many of its 64 lanes are idle (or none is
                                 alive), 1..64; 0 = 16 */
@@ -344,6 +346,26 @@ rt3d_status rt3d_philox4x32_10(const uint32_t* ctr, uint64_t seed,
 rt3d_status rt3d_sobol_entry(uint64_t first_pass, uint32_t n, uint64_t column,
                              uint64_t seed, uint32_t* out, void* stream);
 
+/* The tracer's scattering samplers, element-wise, for tests (sec. 2.3,
+ * phase-function paragraph).  kind 0: Henyey-Greenstein cosine of the
+ * scattering angle by inversion of its distribution,
+ *   mu = (1 + g^2 - s^2) / (2 g),  s = (1 - g^2) / (1 + g (2 xi - 1)),
+ * evaluated for |g| < 0.1 in the multiplied-out form
+ *   mu = (a + g (a^2+3)/2 + g^2 a + g^3 (a^2-1)/2) / (1 + g a)^2, a = 2 xi - 1
+ * (the same function without its cancellation; mu = 2 xi - 1 at g = 0),
+ * clamped to [-1, 1]; mu = 1 for g = 1.  kind 1: Rayleigh (phase function proportional to
+ * 1 + mu^2), mu = u - 1/u with u = cbrt(q + sqrt(q^2 + 1)), q = 4 xi - 2
+ * (g unused, may be NULL).  For i < n: mu[i] = sampler(g[i], xi[i]) with
+ * xi in [0, 1).  DEVICE FP32 arrays [n]. */
+rt3d_status rt3d_phase_sample(int32_t kind, const float* g, const float* xi, float* mu, uint32_t n, void* stream);
+
+/* The tracer's change of direction at a scattering, element-wise, for
+ * tests: unit direction dir_in[3i..3i+2] turned to polar cosine mu[i] about
+ * itself and azimuth 2 pi t[i] (t in [0, 1)) into dir_out[3i..3i+2],
+ * renormalised.  The azimuth's zero is fixed by the kernel's own frame; for
+ * uniform t the result is uniform in azimuth.  DEVICE FP32 arrays. */
+rt3d_status rt3d_turn(const float* dir_in, const float* mu, const float* t, float* dir_out, uint32_t n, void* stream);
+
 /* Clear-sky two-stream column for the flux entering the top of the domain
  * (sec. 2.3, initialisation paragraph: the total incoming flux and its
  * diffuse fraction at the domain top come from a two-stream solution of a
@@ -380,33 +402,6 @@ rt3d_status rt3d_two_stream(int32_t n_cols, int32_t nlay, const double* tau,
                             double* flux_dn_dif, double* flux_up,
                             int32_t tod_level, double* tod_flux,
                             float* tod_diffuse_fraction, void* stream);
-
-/* Memory-system ceiling of the tracer's access pattern, for measurement
- * only (not a step of the method): a persistent grid of 1024-lane
- * workgroups (8 waves per SIMD, as the single-g-point tracer) in which
- * every lane performs `events` dependent random 16-byte gathers from
- * `records` (DEVICE, n_records 16-byte records, 16-byte aligned): the index
- * of each gather is a hash of the record the previous one returned, so a
- * lane has one gather in flight at a time, as a photon's next collision
- * depends on the last.  After `atomics_per_16` of every 16 gathers the lane
- * adds 1 to tally[j] (DEVICE uint64, n_tally entries) at a random j with a
- * 64-bit atomic, as a tentative collision deposits into the heating tallies.
- * Indices are uniform over the arrays (bounded by n_records, n_tally).
- * grid_blocks: workgroups (0 = two per compute unit).  sink (DEVICE FP32,
- * n_sink entries, at least rt3d_access_probe_lanes(grid_blocks)) receives a
- * per-lane sum of the loaded values so no gather is dead.  RT3D_EINVAL on
- * null pointers, zero sizes, n_records or n_tally >= 2^32,
- * atomics_per_16 > 16, records not 16-byte aligned, a short sink.
- * Asynchronous on `stream`; time it with events on that stream. */
-rt3d_status rt3d_access_probe(const void* records, uint64_t n_records,
-                              uint64_t* tally, uint64_t n_tally,
-                              uint32_t events, uint32_t atomics_per_16,
-                              uint32_t grid_blocks, uint64_t seed, float* sink,
-                              uint64_t n_sink, void* stream);
-
-/* Lanes rt3d_access_probe launches for grid_blocks (0 = two workgroups per
- * compute unit of the current device); 0 if the device cannot be queried. */
-uint64_t rt3d_access_probe_lanes(uint32_t grid_blocks);
 
 #ifdef __cplusplus
 }

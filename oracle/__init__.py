@@ -27,11 +27,13 @@ Parity status of each function (what pins it, see ``tests/``):
                                   entry points predicted photon by photon;
                                   the scramble-seed counter is pinned only by
                                   bit-equality with the GPU generator
-  two_stream (module)             exact matrix-exponential propagation of the
-                                  same equations, split-layer invariance, pure
-                                  absorber and conservation closed forms,
-                                  thin-layer backscatter by quadrature, exact
-                                  Monte Carlo transport within 6 %
+  two_stream (module)             the boundary-value problem solved by exact
+                                  matrix-exponential propagation; pinned by the
+                                  adding method with closed-form layers (a
+                                  different algorithm), pure absorber and
+                                  conservation closed forms, thin-layer
+                                  backscatter by quadrature, exact Monte Carlo
+                                  transport within 6 %
 """
 from __future__ import annotations
 

@@ -18,26 +18,42 @@ Readings taken here:
       gamma1 = (8 - w (5 + 3 g)) / 4,  gamma2 = 3 w (1 - g) / 4,
       gamma3 = (2 - 3 mu0 g) / 4,      gamma4 = 1 - gamma3;
 * equations, tau increasing downward, U/D upward/downward diffuse flux,
-  S(tau) = direct horizontal flux, P = S / mu0:
+  P = S / mu0 with S the direct horizontal flux:
       dU/dtau = gamma1 U - gamma2 D - gamma3 w P
       dD/dtau = gamma2 U - gamma1 D + gamma4 w P
       dP/dtau = -P / mu0;
-* each layer is homogeneous; layers are combined with the adding method;
-* the surface is Lambertian with one albedo for direct and diffuse light;
-* gas layers scatter with the Rayleigh phase function (g = 0).
+* boundary conditions: at the TOA no diffuse light comes down (D = 0) and
+  P = the flux normal to the beam; the surface is Lambertian with one
+  albedo for direct and diffuse light, U = albedo (D + mu0 P);
+* each layer is homogeneous; gas layers scatter with the Rayleigh phase
+  function (g = 0).
 
-Parity: pinned in tests/test_two_stream_pins.py against an exact
-matrix-exponential propagation of the same equations through the column
-(no closed forms, no adding), a split-layer invariance, closed forms for a
-pure absorber and energy conservation for conservative scattering.
+The solution is the plain definition of that two-point boundary-value
+problem: in a homogeneous layer y = (U, D, P) obeys dy/dtau = A y with a
+constant matrix A, so y(tau0 + t) = expm(A t) y(tau0) exactly.  Every layer
+is cut into equal sub-layers short enough that expm(A t) grows by at most
+exp(1/2) (this changes nothing in exact arithmetic and keeps the system
+well conditioned), and the transfer relations of all sub-layers plus the
+three boundary conditions form one banded linear system for y at every
+sub-level, solved with LAPACK's banded LU.  No closed-form layer solution,
+no adding method and no special case at the resonance k mu0 = 1 (where
+closed-form particular solutions are singular) are involved.
+
+Parity pins (tests/test_two_stream_pins.py): Beer-Lambert and exp(-2 tau)
+closed forms for a pure absorber, exact energy conservation for
+conservative scattering, single-scattering backscatter of a thin layer by
+quadrature of the phase function, the adding method with closed-form layer
+coefficients (an independent algorithm), and exact Monte Carlo transport
+within the approximation's known accuracy.
 """
 from __future__ import annotations
 
-import numpy as np
+import math
 
-K_MIN = 1e-12          # floor of the eigenvalue k (conservative scattering)
-RESONANCE = 1e-3       # |1 - k^2 mu0^2| below this: resonant layer
-DELTA = 1e-3           # relative shift of mu0 around a resonance
+import numpy as np
+from scipy.linalg import expm, solve_banded
+
+MAX_GROWTH = 0.5       # largest k * t of a sub-layer
 
 
 def gammas(ssa, g, mu0):
@@ -51,57 +67,12 @@ def gammas(ssa, g, mu0):
     return g1, g2, g3, g4
 
 
-def layer(tau, ssa, g, mu0):
-    """Reflection and transmission of one homogeneous layer.
-
-    Returns (R, T, Rdir, Tdir, Tb):
-      R, T     diffuse reflectance and transmittance for diffuse light on
-               either face (the layer is symmetric for diffuse light);
-      Rdir     upward diffuse flux at the top, Tdir downward diffuse flux at
-               the bottom, per unit direct horizontal flux at the top;
-      Tb       exp(-tau/mu0), the unscattered direct transmittance.
-    """
-    g1, g2, g3, g4 = gammas(ssa, g, mu0)
-    k = np.sqrt(np.maximum((g1 - g2) * (g1 + g2), 0.0))
-    k = np.maximum(k, K_MIN)
-    # homogeneous problem (no direct beam): modes exp(+-k tau); with
-    # E = exp(-k tau) and X = 1 - E^2 the two-point problem gives
-    E = np.exp(-k * tau)
-    X = -np.expm1(-2.0 * k * tau)
-    den = k * (1.0 + E * E) + g1 * X
-    R = g2 * X / den
-    T = 2.0 * k * E / den
-    Rdir, Tdir = _direct(tau, ssa, g1, g2, g3, g4, k, R, T, mu0)
-    # the particular solution is singular where k mu0 = 1 although Rdir and
-    # Tdir are smooth there: near that resonance they are the mean of their
-    # values at mu0 (1 - DELTA) and mu0 (1 + DELTA) (error O(DELTA^2), no
-    # division by a small number)
-    near = np.abs(1.0 - k * k * mu0 * mu0) < RESONANCE
-    if np.any(near):
-        both = []
-        for m in (mu0 * (1.0 - DELTA), mu0 * (1.0 + DELTA)):
-            _, _, h3, h4 = gammas(ssa, g, m)
-            both.append(_direct(tau, ssa, g1, g2, h3, h4, k, R, T, m))
-        Rdir = np.where(near, 0.5 * (both[0][0] + both[1][0]), Rdir)
-        Tdir = np.where(near, 0.5 * (both[0][1] + both[1][1]), Tdir)
-    Tb = np.exp(-tau / mu0)
-    return R, T, Rdir, Tdir, Tb
-
-
-def _direct(tau, ssa, g1, g2, g3, g4, k, R, T, mu0):
-    """(Rdir, Tdir) of a layer for the sun at cosine mu0.  Particular
-    solution for unit direct horizontal flux at the top (P0 = 1/mu0):
-    U_p = a exp(-tau/mu0), D_p = b exp(-tau/mu0) with
-      (gamma1 + 1/mu0) a - gamma2 b = gamma3 w P0,
-      gamma2 a + (1/mu0 - gamma1) b = -gamma4 w P0;
-    the homogeneous solution that cancels D at the top (-b) and U at the
-    bottom (-a Tb) is, by the definition of R and T, R and T applied to
-    those two incident fluxes."""
-    d = 1.0 - k * k * mu0 * mu0
-    a = ssa * (g3 * (1.0 - g1 * mu0) - g2 * g4 * mu0) / d
-    b = -ssa * (g4 * (1.0 + g1 * mu0) + g2 * g3 * mu0) / d
-    Tb = np.exp(-tau / mu0)
-    return a - R * b - T * a * Tb, b * Tb - T * b - R * a * Tb
+def system_matrix(ssa: float, g: float, mu0: float) -> np.ndarray:
+    """A of dy/dtau = A y, y = (U, D, P), for one homogeneous layer."""
+    g1, g2, g3, g4 = (float(x) for x in gammas(ssa, g, mu0))
+    return np.array([[g1, -g2, -g3 * ssa],
+                     [g2, -g1, g4 * ssa],
+                     [0.0, 0.0, -1.0 / mu0]])
 
 
 def column(tau, ssa, g, mu0, albedo, flux_toa=1.0):
@@ -109,39 +80,52 @@ def column(tau, ssa, g, mu0, albedo, flux_toa=1.0):
 
     tau, ssa, g: [nlay], layer 0 at the TOA.  flux_toa: solar flux normal
     to the beam at the TOA, so the direct horizontal flux there is
-    flux_toa * mu0.  Returns (direct, down_diffuse, up) [nlay+1], W m^-2 in
-    the units of flux_toa; level 0 is the TOA, level nlay the surface.
+    flux_toa * mu0.  Returns (direct, down_diffuse, up) [nlay+1], in the
+    units of flux_toa; level 0 is the TOA, level nlay the surface."""
+    tau = np.asarray(tau, dtype=np.float64).reshape(-1)
+    ssa = np.asarray(ssa, dtype=np.float64).reshape(-1)
+    g = np.asarray(g, dtype=np.float64).reshape(-1)
+    nlay = tau.size
+    # sub-layers: transfer matrix and count per layer
+    trans, counts = [], []
+    for l in range(nlay):
+        A = system_matrix(ssa[l], g[l], mu0)
+        growth = float(np.max(np.abs(np.linalg.eigvals(A[:2, :2]))))
+        m = max(1, math.ceil(tau[l] * growth / MAX_GROWTH))
+        trans.append(expm(A * (tau[l] / m)))
+        counts.append(m)
+    nsub = int(sum(counts))
+    n = 3 * (nsub + 1)             # unknowns y_0 .. y_nsub, 3 each
+    # equations in order: D_0 = 0, P_0 = F; for each sub-layer s the three
+    # rows y_{s+1} - E y_s = 0; last U_nsub - albedo (D_nsub + mu0 P_nsub) = 0.
+    # Row r of the system has its entries in columns r-2 .. r+3.
+    lo, up = 5, 5
+    ab = np.zeros((lo + up + 1, n))
+    rhs = np.zeros(n)
 
-    Adding method: sweeping up from the surface, Rb[i] is the diffuse albedo
-    of everything below level i and Q[i] the upward diffuse flux at level i
-    produced by the direct beam below level i (with no diffuse light coming
-    down through level i); then sweeping down, the diffuse downward flux
-    follows from multiple reflection between each layer and what lies below
-    it, and U[i] = Rb[i] D[i] + Q[i].
-    """
-    tau = np.asarray(tau, dtype=np.float64)
-    ssa = np.asarray(ssa, dtype=np.float64)
-    g = np.asarray(g, dtype=np.float64)
-    n = tau.size
-    R, T, Rdir, Tdir, Tb = layer(tau, ssa, g, mu0)
-    S = np.empty(n + 1)
-    S[0] = flux_toa * mu0
-    for l in range(n):
-        S[l + 1] = S[l] * Tb[l]
-    Rb = np.empty(n + 1)
-    Q = np.empty(n + 1)
-    Rb[n] = albedo
-    Q[n] = albedo * S[n]
-    for l in range(n - 1, -1, -1):
-        m = 1.0 / (1.0 - R[l] * Rb[l + 1])
-        Rb[l] = R[l] + T[l] * T[l] * Rb[l + 1] * m
-        Q[l] = Rdir[l] * S[l] + T[l] * (Q[l + 1] + Rb[l + 1] * Tdir[l] * S[l]) * m
-    D = np.empty(n + 1)
-    D[0] = 0.0
-    for l in range(n):
-        D[l + 1] = (T[l] * D[l] + Tdir[l] * S[l] + R[l] * Q[l + 1]) / (1.0 - R[l] * Rb[l + 1])
-    U = Rb * D + Q
-    return S, D, U
+    def put(row, col, val):
+        ab[up + row - col, col] = val
+
+    put(0, 1, 1.0)
+    put(1, 2, 1.0)
+    rhs[1] = flux_toa
+    row, s = 2, 0
+    for l in range(nlay):
+        E = trans[l]
+        for _ in range(counts[l]):
+            for i in range(3):
+                for j in range(3):
+                    put(row + i, 3 * s + j, -E[i, j])
+                put(row + i, 3 * (s + 1) + i, 1.0)
+            row += 3
+            s += 1
+    put(row, 3 * nsub, 1.0)
+    put(row, 3 * nsub + 1, -albedo)
+    put(row, 3 * nsub + 2, -albedo * mu0)
+    y = solve_banded((lo, up), ab, rhs).reshape(nsub + 1, 3)
+    levels = np.concatenate([[0], np.cumsum(counts)])
+    Y = y[levels]
+    return mu0 * Y[:, 2], Y[:, 1], Y[:, 0]
 
 
 def top_of_domain(tau, ssa, g, mu0, albedo, level, flux_toa=1.0):

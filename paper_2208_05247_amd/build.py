@@ -1,4 +1,6 @@
-"""Build the HIP library librt3d.so in-tree for gfx950 with hipcc."""
+"""Build the HIP libraries in-tree for gfx950 with hipcc: librt3d.so (the
+tracer, the two-stream column and the denoiser) and librt3d_probe.so (the
+memory-system measurement the benchmark uses; not part of the tracer)."""
 from __future__ import annotations
 
 import os
@@ -7,8 +9,10 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", n) for n in ("rt3d.hip", "denoise.hip", "two_stream.hip", "access_probe.hip")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("rt3d.hip", "denoise.hip", "two_stream.hip")]
 LIB = os.path.join(PKG, "librt3d.so")
+PROBE_SOURCES = [os.path.join(PKG, "csrc", "probe.hip")]
+PROBE_LIB = os.path.join(PKG, "librt3d_probe.so")
 ARCH = os.environ.get("RT3D_OFFLOAD_ARCH", "gfx950")
 
 
@@ -30,14 +34,19 @@ def flags() -> list:
     ]
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile every HIP source into librt3d.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + SOURCES + ["-o", tmp]
+def _compile(sources, lib, verbose):
+    tmp = lib + ".tmp"
+    cmd = [hipcc()] + flags() + sources + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compile librt3d.so and librt3d_probe.so (always recompiles)."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

@@ -110,11 +110,25 @@ __device__ __forceinline__ uint32_t owen_scramble(uint32_t v, uint32_t seed) {
     return out;
 }
 
-// Henyey-Greenstein cos(theta) by inversion of its cumulative distribution.
+// Henyey-Greenstein cos(theta) by inversion of its cumulative distribution,
+// mu = (1 + g^2 - s^2) / (2 g) with s = (1 - g^2) / (1 + g a), a = 2 xi - 1.
+// For small |g| that quotient cancels catastrophically in FP32; multiplied
+// out it is the same function
+//   mu = (a + g (a^2 + 3)/2 + g^2 a + g^3 (a^2 - 1)/2) / (1 + g a)^2,
+// which is exact at g = 0 (mu = a) and well conditioned while 1 + g a stays
+// near 1, so each form is used where it is accurate (|mu error| < 1e-6).
 __device__ __forceinline__ float hg_cos(float g, float xi) {
-    if (fabsf(g) < 1e-3f) return 2.0f * xi - 1.0f;
-    const float s = (1.0f - g * g) / (1.0f - g + 2.0f * g * xi);
-    const float mu = (1.0f + g * g - s * s) / (2.0f * g);
+    if (g >= 1.0f) return 1.0f;  // pure forward scattering (0/0 at xi = 0 otherwise)
+    const float a = 2.0f * xi - 1.0f;
+    float mu;
+    if (fabsf(g) < 0.1f) {
+        const float d = 1.0f + g * a;
+        const float a2 = a * a;
+        mu = (a + g * (0.5f * (a2 + 3.0f) + g * (a + g * (0.5f * (a2 - 1.0f))))) / (d * d);
+    } else {
+        const float s = (1.0f - g * g) / (1.0f - g + 2.0f * g * xi);
+        mu = (1.0f + g * g - s * s) / (2.0f * g);
+    }
     return fminf(1.0f, fmaxf(-1.0f, mu));
 }
 
@@ -842,6 +856,25 @@ __global__ void sobol_entry_kernel(unsigned long long first, uint32_t n, unsigne
     out[i] = make_uint2(owen_scramble<32>(__builtin_bitreverse32(p), sc.x), owen_scramble<32>(sobol_dim2(p), sc.y));
 }
 
+// The tracer's scattering-angle samplers and direction turn, element-wise,
+// for tests: kind 0 = Henyey-Greenstein with g[i], kind 1 = Rayleigh.
+__global__ void phase_sample_kernel(int kind, const float* __restrict__ g, const float* __restrict__ xi,
+                                    float* __restrict__ mu, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) mu[i] = kind == 0 ? hg_cos(g[i], xi[i]) : rayleigh_cos(xi[i]);
+}
+
+__global__ void turn_kernel(const float* __restrict__ din, const float* __restrict__ mu, const float* __restrict__ t,
+                            float* __restrict__ dout, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x = din[3 * i], y = din[3 * i + 1], z = din[3 * i + 2];
+    turn(x, y, z, mu[i], t[i]);
+    dout[3 * i] = x;
+    dout[3 * i + 1] = y;
+    dout[3 * i + 2] = z;
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -974,6 +1007,9 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
     if (!(o.diffuse_fraction >= 0.f && o.diffuse_fraction <= 1.f)) return RT3D_EINVAL;
     if (!(o.rr_threshold >= 0.f && o.rr_threshold <= 1.f)) return RT3D_EINVAL;
     if (o.grid_blocks < 0 || o.block_threads < 0 || o.max_walk < 0 || o.pool_photons < 0) return RT3D_EINVAL;
+    // a refill hands out up to one id per lane of the wave from one grab, so
+    // a grab must hold at least a wave's 64 ids
+    if (o.pool_photons > 0 && o.pool_photons < 64) return RT3D_EINVAL;
     if (o.refill_lanes < 0 || o.refill_lanes > 64) return RT3D_EINVAL;
     if (o.block_threads && o.block_threads != (factored ? Shape_<true>::threads : Shape_<false>::threads))
         return RT3D_EINVAL;
@@ -1300,6 +1336,24 @@ rt3d_status rt3d_sobol_entry(uint64_t first_pass, uint32_t n, uint64_t column, u
     hipLaunchKernelGGL(sobol_entry_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        (unsigned long long)first_pass, n, (unsigned long long)column, (uint32_t)seed,
                        (uint32_t)(seed >> 32), (uint2*)out);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_phase_sample(int32_t kind, const float* g, const float* xi, float* mu, uint32_t n, void* stream) {
+    if ((kind != 0 && kind != 1) || !xi || !mu || (kind == 0 && !g)) return RT3D_EINVAL;
+    if (n == 0) return RT3D_OK;
+    hipLaunchKernelGGL(phase_sample_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, (int)kind, g,
+                       xi, mu, n);
+    HIP_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_turn(const float* dir_in, const float* mu, const float* t, float* dir_out, uint32_t n, void* stream) {
+    if (!dir_in || !mu || !t || !dir_out) return RT3D_EINVAL;
+    if (n == 0) return RT3D_OK;
+    hipLaunchKernelGGL(turn_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, dir_in, mu, t, dir_out,
+                       n);
     HIP_TRY(hipGetLastError());
     return RT3D_OK;
 }

@@ -27,8 +27,10 @@ g-point sets, inputs at 64-1024 photons per column, targets at 16384
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
+import os
 import sys
 import time
 
@@ -38,6 +40,13 @@ import torch
 from . import denoise as dn
 from . import rt3d
 from . import synthetic as syn
+
+# Denoiser weights trained by `python -m paper_2208_05247_amd.experiment
+# --save-weights ...` on the time-to-5 % configuration (25 x 25 x 20 m cells,
+# two-stream entry); BF16 weights and FP32 biases, identified by the sha256
+# of their contents (training is bitwise reproducible).
+WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "denoiser_25x25x20m.npz")
+WEIGHTS_SHA256 = None
 
 F_TOD = 1000.0     # W m^-2, nominal total (direct + diffuse) downward flux at the domain top
 CP = 1004.0        # J kg^-1 K^-1
@@ -139,6 +148,15 @@ class Tracer:
         return fin["abs_dir"], fin["abs_dif"], kms, total
 
 
+def reference_noise(ref_a: torch.Tensor, ref_b: torch.Tensor) -> float:
+    """Relative RMS noise of the reference (the mean of the two halves):
+    sqrt(var_ref / (mean ref^2 - var_ref)), var_ref = mean (a - b)^2 / 4."""
+    ref = 0.5 * (ref_a.double() + ref_b.double())
+    var_ref = float(((ref_a.double() - ref_b.double()) ** 2).mean().item()) / 4.0
+    power = float((ref ** 2).mean().item()) - var_ref
+    return math.sqrt(var_ref / power)
+
+
 def eps_against(h: torch.Tensor, ref_a: torch.Tensor, ref_b: torch.Tensor) -> float:
     ref = 0.5 * (ref_a.double() + ref_b.double())
     var_ref = float(((ref_a.double() - ref_b.double()) ** 2).mean().item()) / 4.0
@@ -209,9 +227,61 @@ def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: in
     return losses, t_steps / max(step, 1)
 
 
+def _weight_arrays(net: dn.Denoiser) -> dict:
+    arr = {}
+    for k in sorted(net.p):
+        arr[f"w_{k}"] = net.pb[k].contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
+        arr[f"b_{k}"] = net.bias[k].cpu().numpy().astype(np.float32)
+    return arr
+
+
+def weights_sha256(arr: dict) -> str:
+    h = hashlib.sha256()
+    for k in sorted(arr):
+        h.update(k.encode())
+        h.update(np.ascontiguousarray(arr[k]).tobytes())
+    return h.hexdigest()
+
+
+def save_denoiser(net: dn.Denoiser, path: str) -> str:
+    """Store the network's BF16 weights (as uint16 bits) and FP32 biases;
+    returns the sha256 of the contents."""
+    arr = _weight_arrays(net)
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, **arr)
+    return weights_sha256(arr)
+
+
+def load_denoiser(path: str, expect_sha256=None):
+    """A Denoiser(base=32) with the stored weights (inference is bitwise that
+    of the network that was saved).  Raises if the contents' sha256 differs
+    from expect_sha256 (when given)."""
+    with np.load(path, allow_pickle=False) as z:
+        arr = {k: z[k] for k in z.files}
+    sha = weights_sha256(arr)
+    if expect_sha256 is not None and sha != expect_sha256:
+        raise RuntimeError(f"{path}: weights sha256 {sha} != expected {expect_sha256}")
+    net = dn.Denoiser(base=32, seed=0)
+    st = {}
+    for k in net.p:
+        bits = torch.from_numpy(arr[f"w_{k}"].view(np.int16).copy())
+        st[f"w_{k}"] = bits.view(torch.bfloat16).float().reshape(net.p[k].shape).cuda()
+        st[f"b_{k}"] = torch.from_numpy(arr[f"b_{k}"]).cuda()
+    net.load_state(st)
+    return net, {"path": os.path.relpath(path, os.path.dirname(os.path.dirname(os.path.abspath(__file__)))),
+                 "sha256": sha}
+
+
+def load_committed_denoiser():
+    if WEIGHTS_SHA256 is None:
+        raise RuntimeError("no committed denoiser weights")
+    return load_denoiser(WEIGHTS_PATH, WEIGHTS_SHA256)
+
+
 def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4096),
-             low=(64, 128, 192, 256, 320, 384, 512, 768, 1024), tod_entry: bool = True):
-    tr = Tracer(wl, tod_entry=tod_entry)
+             low=(64, 128, 192, 256, 320, 384, 512, 768, 1024), tod_entry: bool = True,
+             tracer: "Tracer" = None):
+    tr = tracer if tracer is not None else Tracer(wl, tod_entry=tod_entry)
     g = tr.grid
     log("reference halves ...")
     half = ref_per_col // 2
@@ -219,7 +289,8 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
     ref_a = (a_dir + a_dif).clone()
     b_dir, b_dif, kb, _ = tr.heating(half, seed=525_000_000)
     ref_b = (b_dir + b_dif).clone()
-    log(f"reference kernel ms {ka:.1f} + {kb:.1f}")
+    noise_ref = reference_noise(ref_a, ref_b)
+    log(f"reference kernel ms {ka:.1f} + {kb:.1f}; its own relative noise {noise_ref:.4f}")
     plain = []
     for n in sweep:
         hd, hf, kms, total = tr.heating(n, seed=1_000_000 * (1 + n))
@@ -251,8 +322,10 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
             reached = rec
             break
     res = {"plain_fit": {"a": a, "photons_per_column_at_5pct": n5, "t0_ms": t0, "ms_per_unit_N": c,
-                         "time_to_5pct_ms": t_plain},
+                         "time_to_5pct_ms": t_plain, "sweep_photons_per_column": list(sweep),
+                         "extrapolation_factor": n5 / max(sweep)},
            "plain_sweep": plain, "denoised": den, "reference_photons_per_column": ref_per_col,
+           "reference_relative_noise": noise_ref, "reference_kernel_ms": ka + kb,
            "entry": "two-stream top of domain" if tod_entry else "sun beam, TOA flux weights", **tr.entry}
     if reached:
         t_dn = reached["trace_ms"] + reached["inference_ms"]
@@ -318,6 +391,12 @@ def main():
                          "(instead of the two-stream flux at the domain top)")
     ap.add_argument("--config3", action="store_true",
                     help="train/evaluate on 256x256x96 fields (4-photon inputs, 1024-photon targets) instead")
+    ap.add_argument("--target-photons", type=int, default=16384, help="photons per column of training targets")
+    ap.add_argument("--reference", type=int, default=1 << 17,
+                    help="photons per column of the evaluation reference (two halves)")
+    ap.add_argument("--save-weights", default=None, help="store the trained weights here (.npz)")
+    ap.add_argument("--weights", default=None, help="evaluate these stored weights instead of training")
+    ap.add_argument("--no-eval", action="store_true", help="train (and save) only")
     args = ap.parse_args()
     if args.config3:
         config3(args.out)
@@ -326,20 +405,33 @@ def main():
     if args.quick:
         tr_nx, ev_nx, nz, dx, dz, nf, ref = 64, 128, 64, 25.0, 20.0, 6, 4096
     else:
-        tr_nx, ev_nx, nz, dx, dz, nf, ref = 128, 1024, 128, 25.0, 20.0, args.train_fields, 16384
-    net = dn.Denoiser(base=32, seed=0)
-    log(f"denoiser parameters: {net.n_params()}")
-    t0 = time.perf_counter()
-    losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz,
-                           high=2048 if args.quick else 16384, tod_entry=not args.sun_entry)
-    train_s = time.perf_counter() - t0
-    wl = scene(99_999, ev_nx, ev_nx, nz, dx, dz, sza=60.0, az=0.0, photons=1 << 30)
-    res = evaluate(net, wl, ref, tod_entry=not args.sun_entry)
-    res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,
-                "ms_per_train_step": 1e3 * step_s,
-                "final_train_loss": float(np.mean(losses[-20:])),
-                "eval_grid": [ev_nx, ev_nx, nz], "cell_m": [dx, dx, dz], "sza": 60.0, "g_points": 112,
-                "train_grid": [tr_nx, tr_nx, nz]})
+        tr_nx, ev_nx, nz, dx, dz, nf, ref = 128, 1024, 128, 25.0, 20.0, args.train_fields, args.reference
+    res = {}
+    if args.weights:
+        net, winfo = load_denoiser(args.weights)
+        res["weights"] = winfo
+        train_s = None
+    else:
+        net = dn.Denoiser(base=32, seed=0)
+        log(f"denoiser parameters: {net.n_params()}")
+        t0 = time.perf_counter()
+        losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz,
+                               high=2048 if args.quick else args.target_photons, tod_entry=not args.sun_entry)
+        train_s = time.perf_counter() - t0
+        res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,
+                    "ms_per_train_step": 1e3 * step_s, "target_photons_per_column": args.target_photons,
+                    "final_train_loss": float(np.mean(losses[-20:])), "train_grid": [tr_nx, tr_nx, nz]})
+        if args.save_weights:
+            res["weights_sha256"] = save_denoiser(net, args.save_weights)
+            log(f"weights saved to {args.save_weights}, sha256 {res['weights_sha256']}")
+    if not args.no_eval:
+        wl = scene(99_999, ev_nx, ev_nx, nz, dx, dz, sza=60.0, az=0.0, photons=1 << 30)
+        res.update(evaluate(net, wl, ref, tod_entry=not args.sun_entry))
+        res.update({"eval_grid": [ev_nx, ev_nx, nz], "cell_m": [dx, dx, dz], "sza": 60.0, "g_points": 112})
+        if train_s is not None and res.get("speedup"):
+            # scenes after which training has paid for itself
+            saved = (res["plain_fit"]["time_to_5pct_ms"] - res["denoised_time_to_5pct_ms"]) * 1e-3
+            res["break_even_scenes"] = train_s / saved if saved > 0 else None
     log(json.dumps(res))
     if args.out:
         with open(args.out, "w") as f:

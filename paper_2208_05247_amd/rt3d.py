@@ -30,7 +30,7 @@ EXPORTS = ("rt3d_abi_version", "rt3d_status_string", "rt3d_last_device_error",
            "rt3d_default_options", "rt3d_workspace_size", "rt3d_majorant_build",
            "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize", "rt3d_philox4x32_10",
            "rt3d_workspace_size_batched", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream",
-           "rt3d_access_probe", "rt3d_access_probe_lanes")
+           "rt3d_phase_sample", "rt3d_turn")
 MAX_GPOINTS = 256
 
 
@@ -107,13 +107,11 @@ def load(path: str = LIB_PATH):
     lib.rt3d_sobol_entry.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
     lib.rt3d_two_stream.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, ctypes.c_double, P, P, P, P,
                                     ctypes.c_int32, P, P, P]
-    lib.rt3d_access_probe.argtypes = [P, ctypes.c_uint64, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                      ctypes.c_uint32, ctypes.c_uint64, P, ctypes.c_uint64, P]
-    lib.rt3d_access_probe_lanes.argtypes = [ctypes.c_uint32]
-    lib.rt3d_access_probe_lanes.restype = ctypes.c_uint64
+    lib.rt3d_phase_sample.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_uint32, P]
+    lib.rt3d_turn.argtypes = [P, P, P, P, ctypes.c_uint32, P]
     for name in ("rt3d_majorant_build", "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize",
                  "rt3d_philox4x32_10", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream",
-                 "rt3d_access_probe"):
+                 "rt3d_phase_sample", "rt3d_turn"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.rt3d_abi_version() != 2:
         raise RuntimeError("librt3d.so ABI version mismatch")
@@ -385,23 +383,35 @@ def sobol_entry(first_pass: int, n: int, column: int, seed: int, device="cuda", 
     return out
 
 
-def access_probe(records: torch.Tensor, tally: torch.Tensor, events: int, atomics_per_16: int,
-                 grid_blocks: int = 0, seed: int = 1, stream=None) -> torch.Tensor:
-    """rt3d_access_probe over caller-owned device tensors: `records` with a
-    multiple of 16 bytes per record (e.g. float32 [n, 4]), `tally` int64
-    [m] (used as uint64).  Returns the per-lane sink (FP32 device)."""
-    _require_device(tally, "tally", torch.int64)
-    if records.device.type != "cuda" or not records.is_contiguous() or records.numel() * records.element_size() < 16:
-        raise ValueError("records must be a contiguous device tensor of 16-byte records")
-    n_rec = records.numel() * records.element_size() // 16
-    lanes = int(load().rt3d_access_probe_lanes(int(grid_blocks)))
-    if lanes == 0:
-        raise RuntimeError("rt3d_access_probe_lanes: no HIP device")
-    sink = torch.empty(lanes, dtype=torch.float32, device=records.device)
-    _check(load().rt3d_access_probe(ctypes.c_void_p(records.data_ptr()), n_rec, ctypes.c_void_p(tally.data_ptr()),
-                                    tally.numel(), int(events), int(atomics_per_16), int(grid_blocks), int(seed),
-                                    ctypes.c_void_p(sink.data_ptr()), lanes, _stream(stream)), "rt3d_access_probe")
-    return sink
+def phase_sample(kind: str, xi: torch.Tensor, g: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """rt3d_phase_sample: the tracer's cos(scattering angle) for each xi
+    (FP32 device tensor); kind "hg" (needs g, same shape) or "rayleigh"."""
+    _require_device(xi, "xi", torch.float32)
+    k = {"hg": 0, "rayleigh": 1}[kind]
+    if k == 0:
+        _require_device(g, "g", torch.float32)
+        if g.shape != xi.shape:
+            raise ValueError("g and xi must have the same shape")
+    out = torch.empty_like(xi)
+    gp = ctypes.c_void_p(g.data_ptr()) if g is not None else ctypes.c_void_p(0)
+    _check(load().rt3d_phase_sample(k, gp, ctypes.c_void_p(xi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    xi.numel(), _stream(stream)), "rt3d_phase_sample")
+    return out
+
+
+def turn(d: torch.Tensor, mu: torch.Tensor, t: torch.Tensor, stream=None) -> torch.Tensor:
+    """rt3d_turn: directions d [n, 3] turned by polar cosine mu [n] and
+    azimuth 2 pi t [n] (FP32 device tensors)."""
+    for name, a in (("d", d), ("mu", mu), ("t", t)):
+        _require_device(a, name, torch.float32)
+    n = mu.numel()
+    if d.shape != (n, 3) or t.numel() != n:
+        raise ValueError("d must be [n, 3], mu and t [n]")
+    out = torch.empty_like(d)
+    _check(load().rt3d_turn(ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(mu.data_ptr()),
+                            ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(out.data_ptr()), n, _stream(stream)),
+           "rt3d_turn")
+    return out
 
 
 def two_stream(tau: torch.Tensor, ssa: torch.Tensor, g: torch.Tensor, albedo: torch.Tensor, mu0: float,

@@ -1,13 +1,11 @@
 """Host logic of bench.py (no GPU): the algorithmic-bytes model of the
-tracing kernel, the two readouts gated on the hashes of the sources their
-committed summaries were measured with, and the refusal of more than one
-GPU."""
+tracing kernel, the traffic readout gated on the hash of the kernel source
+and the workload its committed summary was measured with, and the refusal of
+more than one GPU."""
 import os
 import shutil
 import subprocess
 import sys
-
-import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -22,34 +20,41 @@ def test_algorithmic_bytes_per_event():
     assert bench.algorithmic_bytes(stats) == 16 * 1000 + 4 * 310 + 4 * 300 + 20 * 50 + 8 * 40
 
 
-def test_committed_summaries_match_the_sources():
-    """The committed profile summaries were taken on the current sources,
-    so both readouts are live (this guards against committing a changed
-    kernel without re-profiling)."""
-    t = bench.measured_traffic((8, 8, 8), 1 << 26)
-    assert t is not None and t > 1e10
-    r = bench.time_to_5pct()
-    assert r is not None and r["speedup"] > 1.0
-    assert r["plain_time_to_5pct_s"] > r["denoised_time_to_5pct_s"] > 0.0
+def test_roofline_fields():
+    stats = {"collisions": 2000, "scat_gas": 0, "scat_cloud": 0, "surface": 0, "escape": 0}
+    r = bench.tracer_roofline(stats, 2, 1e-3, 64e3)
+    # 16 kB per launch in 1 microsecond = 16 GB/s
+    assert abs(r["achieved"] - 16.0) < 1e-9 and abs(r["frac"] - 16.0 / 8000.0) < 1e-12
+    assert abs(r["traffic_GBps"] - 64.0) < 1e-9
+    assert bench.tracer_roofline(stats, 2, 1e-3, None)["traffic"] is None
 
 
-def test_readouts_are_gated(tmp_path, monkeypatch):
-    """Another workload, or any change to a hashed source, turns the
-    readouts off."""
-    assert bench.measured_traffic((4, 4, 4), 1 << 26) is None
-    assert bench.measured_traffic((8, 8, 8), 1 << 20) is None
+def test_traffic_readout_is_gated(tmp_path, monkeypatch):
+    """The readout is live only for the kernel source hash and workload the
+    summary names; any change to the source, or another workload, turns it
+    off."""
     copy = tmp_path / "repo"
-    for d in ("profiles", os.path.join("paper_2208_05247_amd", "csrc")):
-        shutil.copytree(os.path.join(ROOT, d), copy / d)
-    for f in ("denoise.py", "experiment.py"):
-        shutil.copy(os.path.join(ROOT, "paper_2208_05247_amd", f), copy / "paper_2208_05247_amd" / f)
+    shutil.copytree(os.path.join(ROOT, "paper_2208_05247_amd", "csrc"), copy / "paper_2208_05247_amd" / "csrc")
+    (copy / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(copy))
-    assert bench.measured_traffic((8, 8, 8), 1 << 26) is not None
-    assert bench.time_to_5pct() is not None
+    sha = bench.source_hash(bench.TRACER_SOURCES)
+    (copy / "profiles" / "p.md").write_text(
+        "# summary\n\n    source_sha256_16: %s\n    workload: wl_a\n    traffic_bytes_per_launch: 123456789\n" % sha)
+    assert bench.measured_traffic("p.md", "wl_a") == 123456789.0
+    assert bench.measured_traffic("p.md", "wl_b") is None
+    assert bench.measured_traffic("missing.md", "wl_a") is None
     src = copy / "paper_2208_05247_amd" / "csrc" / "rt3d.hip"
     src.write_text(src.read_text() + "\n// changed\n")
-    assert bench.measured_traffic((8, 8, 8), 1 << 26) is None
-    assert bench.time_to_5pct() is None
+    assert bench.measured_traffic("p.md", "wl_a") is None
+
+
+def test_committed_traffic_summaries_name_their_workload():
+    """Every committed tracing-kernel summary states the source hash and the
+    workload its figures belong to."""
+    for name in os.listdir(os.path.join(ROOT, "profiles")):
+        if name.startswith("trace_kernel_"):
+            f = bench.profile_fields(name)
+            assert "source_sha256_16" in f and "workload" in f, name
 
 
 def test_more_than_one_gpu_is_refused():

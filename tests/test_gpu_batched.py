@@ -101,7 +101,7 @@ def test_launch_options_do_not_change_tallies(rt3d, kw):
 
 def test_batched_parity_vs_oracle(rt3d):
     """Broadband tallies of 6 g-points (gas optical depth 1e-3..50) vs the
-    oracle traced per g-point on materialised fields, 32 batches each.  The
+    oracle traced per g-point on materialised fields, 64 batches each.  The
     scene has bricks without cloud (where the kernel reads no cell record)
     and bricks with cloud."""
     wl = small_batch(n_gp=6, photons=1 << 15, seed=5)
@@ -112,7 +112,7 @@ def test_batched_parity_vs_oracle(rt3d):
     total = sum(counts)
     dm = rt3d.DeviceBatchedMedium.from_host(m)
     grid = m.grid
-    B = 32
+    B = 64
     gpu = {k: [] for k in ARRAYS}
     ora = {k: [] for k in ARRAYS}
     fields = [m.fields_of(n) for n in range(m.n_gpoints)]
@@ -139,7 +139,7 @@ def test_batched_parity_vs_oracle(rt3d):
         g, o = np.stack(gpu[k]), np.stack(ora[k])
         frac, n_dense, _, dense, z = compare_batches(g, o)
         say("batched", k, frac, n_dense)
-        assert frac >= 0.998 and np.all(np.abs(z[dense]) < 5.5), k
+        assert frac >= 0.999 and np.all(np.abs(z[dense]) < 8.0), k
         if k.startswith("abs"):
             ga, oa = g.sum(axis=(2, 3)), o.sum(axis=(2, 3))
         else:

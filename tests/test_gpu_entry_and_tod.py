@@ -85,11 +85,11 @@ def test_sobol_vacuum_landing_columns(rt3d, per, sza, az, seed):
 
 
 def test_sobol_parity_small_cumulus(rt3d):
-    """32x32x64 cumulus, 32 batches of 2^14 photons with Sobol entry, GPU vs
+    """32x32x64 cumulus, 64 batches of 2^14 photons with Sobol entry, GPU vs
     oracle (independent seeds), 4-SE rule per cell."""
     wl = syn.small_cumulus()
     df = rt3d.DeviceFields.from_host(wl.fields)
-    B, per = 32, 1 << 14
+    B, per = 64, 1 << 14
     g = {k: [] for k in ARRAYS}
     o = {k: [] for k in ARRAYS}
     for b in range(B):
@@ -103,7 +103,7 @@ def test_sobol_parity_small_cumulus(rt3d):
     for k in ARRAYS:
         frac, n_dense, _, dense, z = compare_batches(np.stack(g[k]), np.stack(o[k]))
         say("sobol parity", k, round(frac, 5), n_dense)
-        assert frac >= 0.998, k
+        assert frac >= 0.999 and np.all(np.abs(z[dense]) < 8.0), k
 
 
 def test_sobol_lowers_column_noise_on_gpu(rt3d):
@@ -149,7 +149,11 @@ def columns(rng, ncol, nlay, mu0):
 def test_two_stream_parity(rt3d):
     """112 columns x 150 layers (optical depth 1e-4..3 per layer, conservative,
     pure-absorbing and resonant layers, black and white surfaces) against the
-    FP64 oracle at every level, and the TOD flux / diffuse fraction."""
+    FP64 oracle (the boundary-value problem solved by matrix-exponential
+    propagation) at every level, and the TOD flux / diffuse fraction.  The
+    kernel's closed-form layer solution is exact away from the resonance
+    k mu0 = 1 (1e-9 relative); in the two columns with resonant layers its
+    mean of the two sides of the resonance is good to 2e-6."""
     g1, g2, _, _ = ots.gammas(0.5, 0.0, 0.5)
     mu0 = 1.0 / float(np.sqrt((g1 - g2) * (g1 + g2)))
     rng = np.random.default_rng(42)
@@ -157,19 +161,21 @@ def test_two_stream_parity(rt3d):
     tau, ssa, g, alb, ftoa = columns(rng, ncol, nlay, mu0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
     out = rt3d.two_stream(dev(tau), dev(ssa), dev(g), dev(alb), mu0, tod, flux_toa=dev(ftoa))
-    worst = 0.0
+    worst = {False: 0.0, True: 0.0}
     for c in range(ncol):
+        resonant = c in (5, 9)
+        rtol = 2e-6 if resonant else 1e-9
         S, D, U = ots.column(tau[c], ssa[c], g[c], mu0, alb[c], flux_toa=ftoa[c])
         for name, ref in (("dir", S), ("dn_dif", D), ("up", U)):
             got = out[name][c].cpu().numpy()
             scale = ftoa[c] * mu0
             err = np.abs(got - ref) / (np.abs(ref) + 1e-12 * scale)
-            worst = max(worst, float(err.max()))
-            assert np.allclose(got, ref, rtol=1e-10, atol=1e-13 * scale), (c, name)
+            worst[resonant] = max(worst[resonant], float(err.max()))
+            assert np.allclose(got, ref, rtol=rtol, atol=1e-12 * scale), (c, name)
         tot = S[tod] + D[tod]
-        assert out["tod_flux"][c].item() == pytest.approx(tot, rel=1e-10)
-        assert out["tod_diffuse_fraction"][c].item() == pytest.approx(np.float32(D[tod] / tot), rel=2e-7)
-    say("two-stream worst relative error", worst)
+        assert out["tod_flux"][c].item() == pytest.approx(tot, rel=rtol)
+        assert out["tod_diffuse_fraction"][c].item() == pytest.approx(np.float32(D[tod] / tot), rel=2e-7, abs=1e-12)
+    say("two-stream worst relative error: other columns", worst[False], "resonant columns", worst[True])
 
 
 def test_two_stream_degenerate_columns(rt3d):
@@ -247,7 +253,7 @@ def test_two_stream_tod_end_to_end_parity(rt3d):
     each g-point's TOD flux and diffuse fraction (GPU two-stream vs oracle);
     photons go to g-points in proportion to the TOD flux; the batched launch
     with per-g-point diffuse fractions agrees with the oracle traced per
-    g-point with the same fractions, cell by cell (32 batches)."""
+    g-point with the same fractions, cell by cell (64 batches)."""
     wl = small_batch(n_gp=6, photons=1 << 15, seed=5)
     m = wl.medium
     tau, ssa, g = syn.clear_sky_columns(m, n_above=32)
@@ -260,8 +266,8 @@ def test_two_stream_tod_end_to_end_parity(rt3d):
     ftod = ts_out["tod_flux"].cpu().numpy()
     for n in range(m.n_gpoints):
         tot, frac = ots.top_of_domain(tau[n], ssa[n], g[n], mu0, alb[n], 32, flux_toa=ftoa[n])
-        assert ftod[n] == pytest.approx(tot, rel=1e-10)
-        assert fd[n].item() == pytest.approx(np.float32(frac), rel=2e-7)
+        assert ftod[n] == pytest.approx(tot, rel=1e-9)
+        assert fd[n].item() == pytest.approx(np.float32(frac), rel=2e-7, abs=1e-12)
     say("TOD flux", np.round(ftod, 3), "diffuse fraction", np.round(fd.cpu().numpy(), 4))
     rng = np.random.default_rng(8)
     counts = [int(c) for c in rng.multinomial(1 << 15, ftod / ftod.sum())]
@@ -269,7 +275,7 @@ def test_two_stream_tod_end_to_end_parity(rt3d):
     dm = rt3d.DeviceBatchedMedium.from_host(m)
     fields = [m.fields_of(n) for n in range(m.n_gpoints)]
     fdh = fd.cpu().numpy()
-    B = 32
+    B = 64
     gpu = {k: [] for k in ARRAYS}
     ora = {k: [] for k in ARRAYS}
     for b in range(B):
@@ -290,7 +296,7 @@ def test_two_stream_tod_end_to_end_parity(rt3d):
     for k in ARRAYS:
         frac, n_dense, _, dense, z = compare_batches(np.stack(gpu[k]), np.stack(ora[k]))
         say("tod parity", k, round(frac, 5), n_dense)
-        assert frac >= 0.998, k
+        assert frac >= 0.999 and np.all(np.abs(z[dense]) < 8.0), k
 
 
 def test_experiment_entry_shares_and_fractions(rt3d):

@@ -11,10 +11,13 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rt3d.h")
+PKG = os.path.join(ROOT, "paper_2208_05247_amd")
+# every public header and the library that implements it
+HEADER_LIBS = {"rt3d.h": "librt3d.so", "rt3d_denoise.h": "librt3d.so", "rt3d_probe.h": "librt3d_probe.so"}
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(rt3d_[a-z0-9_]+)\s*\(", src)))
 
@@ -38,6 +41,26 @@ def test_exports_match_header(lib):
     for f in decl:
         assert hasattr(lib, f)
     assert set(rt3d.EXPORTS) <= set(decl)
+
+
+@pytest.mark.parametrize("header", sorted(HEADER_LIBS))
+def test_every_header_is_exported_by_its_library(header):
+    """Each public header's functions are defined by its library, and the
+    measurement probe is not part of the tracer library."""
+    inc = os.path.join(ROOT, "include")
+    assert sorted(os.listdir(inc)) == sorted(HEADER_LIBS)
+    so = os.path.join(PKG, HEADER_LIBS[header])
+    if not os.path.exists(so):
+        pytest.fail(f"{so} is not built (run __graft_entry__.build())")
+    decl = declared_functions(os.path.join(inc, header))
+    assert decl
+    out = subprocess.check_output(["nm", "-D", "--defined-only", so], text=True)
+    exported = set(re.findall(r"\bT (rt3d_[a-z0-9_]+)", out))
+    assert not [f for f in decl if f not in exported]
+    tracer = set(re.findall(r"\bT (rt3d_[a-z0-9_]+)",
+                            subprocess.check_output(["nm", "-D", "--defined-only",
+                                                     os.path.join(PKG, "librt3d.so")], text=True)))
+    assert not [f for f in tracer if "probe" in f]
 
 
 def test_abi_and_strings(lib):
@@ -104,14 +127,47 @@ def test_einval_before_any_launch(lib):
     assert ts(2, 5, *args, 1.5, None, fake, fake, fake, 0, None, None, None) == rt3d.EINVAL   # mu0 > 1
     assert ts(2, 5, *args, 0.5, None, fake, fake, fake, 6, None, None, None) == rt3d.EINVAL   # level > nlay
     assert ts(2, 5, *args, 0.5, None, None, fake, fake, 0, None, None, None) == rt3d.EINVAL   # no output
-    ap = lib.rt3d_access_probe
-    assert ap(None, 16, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL            # no records
-    assert ap(fake, 0, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL             # empty
-    assert ap(fake, 1 << 32, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL       # too many records
-    assert ap(fake, 16, fake, 16, 8, 17, 4, 1, fake, 4096, None) == rt3d.EINVAL            # > 16 of 16
-    assert ap(ctypes.c_void_p(264), 16, fake, 16, 8, 11, 4, 1, fake, 4096, None) == rt3d.EINVAL  # misaligned
-    assert ap(fake, 16, fake, 16, 8, 11, 4, 1, fake, 4095, None) == rt3d.EINVAL            # short sink
-    assert lib.rt3d_access_probe_lanes(5) == 5 * 1024
+
+
+def test_probe_argument_checks():
+    """The memory probe's host checks reject bad arguments before any launch."""
+    from paper_2208_05247_amd import probe
+    lib = probe.load()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the host checks reject first
+    ap = lib.rt3d_probe_gathers
+    assert ap(None, 16, fake, 16, 8, 1, 11, 0, 4, 1, fake, 4096, None) == 1            # no records
+    assert ap(fake, 0, fake, 16, 8, 1, 11, 0, 4, 1, fake, 4096, None) == 1             # empty
+    assert ap(fake, 1 << 32, fake, 16, 8, 1, 11, 0, 4, 1, fake, 4096, None) == 1       # too many records
+    assert ap(fake, 16, fake, 16, 8, 1, 17, 0, 4, 1, fake, 4096, None) == 1            # > 16 of 16
+    assert ap(ctypes.c_void_p(264), 16, fake, 16, 8, 1, 11, 0, 4, 1, fake, 4096, None) == 1  # misaligned
+    assert ap(fake, 16, fake, 16, 8, 1, 11, 0, 4, 1, fake, 4095, None) == 1            # short sink
+    assert ap(fake, 16, fake, 16, 8, 0, 11, 0, 4, 1, fake, 4096, None) == 1            # no chain
+    assert ap(fake, 16, fake, 16, 8, 5, 11, 0, 4, 1, fake, 4096, None) == 1            # too many chains
+    assert ap(fake, 16, fake, 16, 8, 1, 11, 2, 4, 1, fake, 4096, None) == 1            # unknown flag
+    assert ap(ctypes.c_void_p(272), 16, fake, 16, 8, 1, 11, 1, 4, 1, fake, 4096, None) == 1  # pair: 128-B align
+    assert ap(fake, 12, fake, 16, 8, 1, 11, 1, 4, 1, fake, 4096, None) == 1            # pair: n % 8
+    assert lib.rt3d_probe_lanes(5) == 5 * 1024
+
+
+def test_small_photon_pools_rejected(lib):
+    """A refill hands out up to 64 photon ids from one grab of the work
+    queue, so pools of 1..63 ids would hand out ids of the next grab (photons
+    traced twice): they are rejected on the host, before any launch."""
+    from paper_2208_05247_amd import rt3d
+    g = rt3d.Grid(8, 8, 8, 10.0, 10.0, 10.0)
+    fake = ctypes.c_void_p(256)  # never dereferenced: the host checks reject first
+    props = rt3d.OpticalProps(256, 256, 256, 256)
+    t = rt3d.TalliesStruct(*([256] * 8))
+    med = rt3d.BatchedMedium(256, 256, 256, 256, 256, None)
+    counts = (ctypes.c_uint64 * 2)(100, 50)
+    for pool in (1, 32, 63, -1):
+        o = rt3d.options(brick=(4, 4, 4), pool_photons=pool)
+        ws = rt3d.workspace_size(g, o)
+        assert lib.rt3d_trace(ctypes.byref(g), ctypes.byref(props), fake, 30.0, 0.0, 100, 1, ctypes.byref(o),
+                              ctypes.byref(t), fake, ws, None) == rt3d.EINVAL, pool
+        wsb = rt3d.workspace_size_batched(g, 2, o)
+        assert lib.rt3d_trace_batched(ctypes.byref(g), 2, ctypes.byref(med), counts, fake, 30.0, 0.0, 1,
+                                      ctypes.byref(o), ctypes.byref(t), fake, wsb, None) == rt3d.EINVAL, pool
 
 
 def test_product_path_has_no_fallback():

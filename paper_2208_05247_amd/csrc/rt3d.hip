@@ -139,19 +139,24 @@ __device__ __forceinline__ float rayleigh_cos(float xi) {
     return fminf(1.0f, fmaxf(-1.0f, u - rcp(u)));
 }
 
-// Turn direction (x,y,z) by polar cosine mu and azimuth 2*pi*t.
+// Turn direction (x,y,z) by polar cosine mu and azimuth 2*pi*t, in the
+// frame e1 = (x z, y z, -s^2)/s, e2 = (-y, x, 0)/s with s = |(x, y)|.  s is
+// taken from the horizontal components (not sqrt(1 - z^2), which cancels for
+// near-vertical d), so the frame stays accurate down to s ~ 1e-12; only a
+// direction closer to vertical than that uses the fixed frame (x, y axes).
 __device__ __forceinline__ void turn(float& x, float& y, float& z, float mu, float t) {
     float sp, cp;
     __sincosf(6.28318530717958647f * t, &sp, &cp);
     const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
     float nx, ny, nz;
-    if (fabsf(z) > 0.99999f) {
+    const float s2 = x * x + y * y;
+    if (s2 < 1e-24f) {
         nx = st * cp;
         ny = st * sp;
         nz = z > 0.0f ? mu : -mu;
     } else {
-        const float s = sqrtf(1.0f - z * z);
-        const float is = rcp(s);
+        const float is = rsqrtf(s2);
+        const float s = s2 * is;
         nx = st * (x * z * cp - y * sp) * is + x * mu;
         ny = st * (y * z * cp + x * sp) * is + y * mu;
         nz = -st * cp * s + z * mu;

@@ -15,8 +15,8 @@
 namespace {
 
 constexpr double kKFloor = 1e-12;     // eigenvalue floor (conservative scattering)
-constexpr double kResonance = 1e-3;   // |1 - k^2 mu0^2| below this: resonant layer
-constexpr double kShift = 1e-3;       // relative mu0 shift around a resonance
+constexpr double kResonance = 1e-5;   // |1 - k^2 mu0^2| below this: resonant layer
+constexpr double kShift = 1e-5;       // relative mu0 shift around a resonance
 
 struct LayerRT {
     double R, T;        // diffuse reflectance / transmittance (either face)
@@ -55,6 +55,8 @@ __device__ LayerRT layer_rt(double tau, double w, double g, double mu0) {
     L.T = 2.0 * k * e / den;
     if (fabs(1.0 - k * k * mu0 * mu0) < kResonance) {
         // singular particular solution, smooth result: mean of both sides
+        // (error O(kShift^2) from the mean; just outside the window the
+        // closed form loses about eps / kResonance to cancellation)
         double r1, t1, r2, t2;
         direct_terms(tau, w, g, g1, g2, k, L.R, L.T, mu0 * (1.0 - kShift), &r1, &t1);
         direct_terms(tau, w, g, g1, g2, k, L.R, L.T, mu0 * (1.0 + kShift), &r2, &t2);

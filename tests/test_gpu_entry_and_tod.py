@@ -152,8 +152,10 @@ def test_two_stream_parity(rt3d):
     FP64 oracle (the boundary-value problem solved by matrix-exponential
     propagation) at every level, and the TOD flux / diffuse fraction.  The
     kernel's closed-form layer solution is exact away from the resonance
-    k mu0 = 1 (1e-9 relative); in the two columns with resonant layers its
-    mean of the two sides of the resonance is good to 2e-6."""
+    k mu0 = 1, and its mean of the two sides of the resonance (mu0 shifted
+    by 1e-5) is good to 1e-10, so every level of every column agrees to
+    1e-9 relative: the two columns with resonant layers and the columns
+    whose random layers come within 1e-3 of it alike."""
     g1, g2, _, _ = ots.gammas(0.5, 0.0, 0.5)
     mu0 = 1.0 / float(np.sqrt((g1 - g2) * (g1 + g2)))
     rng = np.random.default_rng(42)
@@ -164,7 +166,7 @@ def test_two_stream_parity(rt3d):
     worst = {False: 0.0, True: 0.0}
     for c in range(ncol):
         resonant = c in (5, 9)
-        rtol = 2e-6 if resonant else 1e-9
+        rtol = 1e-9
         S, D, U = ots.column(tau[c], ssa[c], g[c], mu0, alb[c], flux_toa=ftoa[c])
         for name, ref in (("dir", S), ("dn_dif", D), ("up", U)):
             got = out[name][c].cpu().numpy()

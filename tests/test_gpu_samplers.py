@@ -82,14 +82,17 @@ def test_rayleigh_sampler(rt3d):
 
 def test_turn(rt3d):
     """Unit length, d . d' = mu, and for uniform azimuths the mean turned
-    direction is mu d (the azimuth is uniform about d), including directions
-    within the kernel's near-vertical special case."""
+    direction is mu d (the azimuth is uniform about d), including exactly
+    vertical directions (the kernel's fixed frame) and directions a few
+    1e-3 to 1e-7 off vertical."""
     rng = np.random.default_rng(4)
     n = 1 << 16
     d = rng.standard_normal((n, 3))
     d[:16] = [0.0, 0.0, 1.0]
     d[16:32] = [0.0, 0.0, -1.0]
     d[32:48] = [1e-4, 0.0, -1.0]
+    d[48:64] = [3e-3, 1e-3, -1.0]
+    d[64:80] = [1e-7, 0.0, 1.0]
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     mu = rng.uniform(-1.0, 1.0, n)
     t = rng.uniform(0.0, 1.0, n)

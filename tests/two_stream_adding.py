@@ -4,7 +4,8 @@ and transmission of each homogeneous layer (the source-free modes
 exp(+-k tau) plus the particular solution of the direct beam), combined
 through the column with the adding method.  Near the resonance k mu0 = 1,
 where the particular solution is singular, a layer's direct-beam terms are
-the mean of their values at mu0 (1 -+ 1e-3), an O(1e-6) approximation.
+the mean of their values at mu0 (1 -+ 1e-5): an O(1e-10) error from the
+mean, O(1e-11) from cancellation just outside the window.
 
 The PIFM coefficients and equations are those stated in
 oracle/two_stream.py (Zdunkowski, Welch and Korb 1980; Meador and Weaver
@@ -14,8 +15,8 @@ from __future__ import annotations
 import numpy as np
 
 K_MIN = 1e-12          # floor of the eigenvalue k (conservative scattering)
-RESONANCE = 1e-3       # |1 - k^2 mu0^2| below this: resonant layer
-DELTA = 1e-3           # relative shift of mu0 around a resonance
+RESONANCE = 1e-5       # |1 - k^2 mu0^2| below this: resonant layer
+DELTA = 1e-5           # relative shift of mu0 around a resonance
 
 
 def gammas(ssa, g, mu0):

@@ -33,7 +33,8 @@
  * Every entry point is `extern "C"`, takes plain pointers and sizes, and
  * reports errors only through `rt3d_status`.  Unless stated otherwise a
  * pointer argument is a DEVICE pointer owned by the caller; the library
- * never allocates or frees device memory.  `stream` is a hipStream_t passed
+ * never allocates or frees device memory (its one static device array, the
+ * scratch of rt3d_trace_noalloc, is part of the loaded code).  `stream` is a hipStream_t passed
  * as `void*` (NULL = the null stream).  All work is enqueued asynchronously
  * on `stream`; results are valid once that stream has completed.  Host-side
  * argument checks run before anything is enqueued, so a call that returns an
@@ -98,7 +99,10 @@ typedef enum {
                          not dividing the grid, sza outside [0,90), photons 0
                          or >= 2^33, workspace too small, too many cells */
     RT3D_EDOMAIN = 2, /* RT3D_FLAG_VALIDATE found a field value out of range */
-    RT3D_EDEVICE = 3  /* a HIP runtime call failed; see rt3d_last_device_error */
+    RT3D_EDEVICE = 3, /* a HIP runtime call failed; see rt3d_last_device_error */
+    RT3D_ETOOBIG = 4  /* rt3d_trace_noalloc: the grid needs more scratch than
+                         RT3D_NOALLOC_SCRATCH_BYTES (text in
+                         rt3d_last_device_error); nothing launched */
 } rt3d_status;
 
 /* Uniform grid; every size positive, nx*ny*nz < 2^31. */
@@ -282,6 +286,28 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props,
                        double azimuth_deg, uint64_t photons, uint64_t seed,
                        const rt3d_options* opt, const rt3d_tallies* out,
                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of static device scratch behind rt3d_trace_noalloc (32 MiB: the
+ * rt3d_trace workspace of grids up to about 2 million cells). */
+#define RT3D_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* rt3d_trace for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and errors as rt3d_trace, but the workspace is a
+ * static device array of RT3D_NOALLOC_SCRATCH_BYTES held by the library on
+ * every device it runs on until the process ends; the caller passes only
+ * inputs and outputs.  The call allocates nothing (no hipMalloc, no events):
+ * RT3D_FLAG_TIME is rejected with RT3D_EINVAL, a grid whose
+ * rt3d_workspace_size exceeds the scratch with RT3D_ETOOBIG.  The device is
+ * the current one; its scratch address is looked up on the first call there
+ * (RT3D_EDEVICE if that fails).  All calls on one device share its scratch
+ * and every call re-initialises what it reads, so sequential calls are
+ * independent; calls that overlap on one device (two streams, two threads)
+ * race and give undefined tallies. */
+rt3d_status rt3d_trace_noalloc(const rt3d_grid* grid, const rt3d_optical_props* props,
+                               const float* surface_albedo, double sza_deg,
+                               double azimuth_deg, uint64_t photons, uint64_t seed,
+                               const rt3d_options* opt, const rt3d_tallies* out, void* stream);
 
 /* Bytes of device workspace rt3d_trace_batched needs (per-g-point majorant
  * grids, packed cloud records, gas tables).  Returns 0 on bad input. */

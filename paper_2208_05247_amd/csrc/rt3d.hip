@@ -1163,6 +1163,42 @@ rt3d_status launch_trace(Launch& L, bool factored, hipStream_t st) {
     return RT3D_OK;
 }
 
+// Scratch of rt3d_trace_noalloc: the workspace of rt3d_trace (control
+// block, photon ranges, majorant grid, packed cell records) in a file-scope
+// device array instead of a caller buffer.  Every device the library runs on
+// holds its own copy for the life of the process.  In host code the array's
+// name is not a device address; its address on each device comes from
+// hipGetSymbolAddress (scratch_address) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[RT3D_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device.
+rt3d_status scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        snprintf(g_err, sizeof g_err, "rt3d_trace_noalloc: device %d beyond the %d it keeps scratch for", dev,
+                 kMaxDevices);
+        return RT3D_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) {
+            snprintf(g_err, sizeof g_err, "rt3d_trace_noalloc: bad scratch address on device %d", dev);
+            return RT3D_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RT3D_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1178,6 +1214,7 @@ const char* rt3d_status_string(rt3d_status s) {
         case RT3D_EINVAL: return "invalid argument";
         case RT3D_EDOMAIN: return "field value out of range";
         case RT3D_EDEVICE: return "HIP device error";
+        case RT3D_ETOOBIG: return "problem larger than the static scratch of rt3d_trace_noalloc";
     }
     return "unknown status";
 }
@@ -1249,6 +1286,27 @@ rt3d_status rt3d_trace(const rt3d_grid* grid, const rt3d_optical_props* props, c
                        props->ssa, props->k_ext_cloud, props->g, L.cells, L.s.ncell);
     HIP_TRY(hipGetLastError());
     return launch_trace(L, false, hs);
+}
+
+rt3d_status rt3d_trace_noalloc(const rt3d_grid* grid, const rt3d_optical_props* props, const float* surface_albedo,
+                               double sza_deg, double azimuth_deg, uint64_t photons, uint64_t seed,
+                               const rt3d_options* opt, const rt3d_tallies* out, void* stream) {
+    g_timed = false;
+    // timing would create HIP events on first use
+    if (opt && (opt->flags & RT3D_FLAG_TIME)) return RT3D_EINVAL;
+    const size_t need = rt3d_workspace_size(grid, opt);
+    if (need == 0) return RT3D_EINVAL;
+    if (need > RT3D_NOALLOC_SCRATCH_BYTES) {
+        snprintf(g_err, sizeof g_err,
+                 "rt3d_trace_noalloc: this grid needs %zu bytes of scratch, more than its %zu", need,
+                 (size_t)RT3D_NOALLOC_SCRATCH_BYTES);
+        return RT3D_ETOOBIG;
+    }
+    void* ws = nullptr;
+    const rt3d_status st = scratch_address(&ws);
+    if (st != RT3D_OK) return st;
+    return rt3d_trace(grid, props, surface_albedo, sza_deg, azimuth_deg, photons, seed, opt, out, ws,
+                      RT3D_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 rt3d_status rt3d_trace_batched(const rt3d_grid* grid, int32_t n_gpoints, const rt3d_batched_medium* medium,

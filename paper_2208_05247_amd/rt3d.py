@@ -19,7 +19,8 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librt3d.so")
 
-OK, EINVAL, EDOMAIN, EDEVICE = 0, 1, 2, 3
+OK, EINVAL, EDOMAIN, EDEVICE, ETOOBIG = 0, 1, 2, 3, 4
+NOALLOC_SCRATCH_BYTES = 32 << 20  # RT3D_NOALLOC_SCRATCH_BYTES
 FLAG_ACCUMULATE, FLAG_VALIDATE, FLAG_TIME, FLAG_NO_MERGE, FLAG_SOBOL_ENTRY = 0x1, 0x2, 0x4, 0x8, 0x10
 LEDGER = ("incoming", "toa", "atm_dir", "atm_dif", "sfc", "rr_gain", "rr_loss", "lost")
 STATS = ("photons", "collisions", "null", "scat_gas", "scat_cloud", "surface", "escape",
@@ -30,7 +31,7 @@ EXPORTS = ("rt3d_abi_version", "rt3d_status_string", "rt3d_last_device_error",
            "rt3d_default_options", "rt3d_workspace_size", "rt3d_majorant_build",
            "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize", "rt3d_philox4x32_10",
            "rt3d_workspace_size_batched", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream",
-           "rt3d_phase_sample", "rt3d_turn")
+           "rt3d_phase_sample", "rt3d_turn", "rt3d_trace_noalloc")
 MAX_GPOINTS = 256
 
 
@@ -95,6 +96,9 @@ def load(path: str = LIB_PATH):
     lib.rt3d_trace.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(OpticalProps), P, ctypes.c_double,
                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Options),
                                ctypes.POINTER(TalliesStruct), P, Z, P]
+    lib.rt3d_trace_noalloc.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(OpticalProps), P, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Options),
+                                       ctypes.POINTER(TalliesStruct), P]
     lib.rt3d_last_trace_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
     lib.rt3d_workspace_size_batched.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, ctypes.POINTER(Options)]
     lib.rt3d_workspace_size_batched.restype = Z
@@ -109,9 +113,9 @@ def load(path: str = LIB_PATH):
                                     ctypes.c_int32, P, P, P]
     lib.rt3d_phase_sample.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_uint32, P]
     lib.rt3d_turn.argtypes = [P, P, P, P, ctypes.c_uint32, P]
-    for name in ("rt3d_majorant_build", "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize",
+    for name in ("rt3d_majorant_build", "rt3d_trace", "rt3d_trace_noalloc", "rt3d_last_trace_ms", "rt3d_finalize",
                  "rt3d_philox4x32_10", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream",
-                 "rt3d_phase_sample", "rt3d_turn"):
+                 "rt3d_phase_sample", "rt3d_turn", "rt3d_trace_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.rt3d_abi_version() != 2:
         raise RuntimeError("librt3d.so ABI version mismatch")
@@ -128,7 +132,7 @@ def _status_text(status: int) -> str:
 
 def _check(status: int, what: str):
     if status != OK:
-        detail = load().rt3d_last_device_error().decode() if status == EDEVICE else ""
+        detail = load().rt3d_last_device_error().decode() if status in (EDEVICE, ETOOBIG) else ""
         raise Rt3dError(status, what, detail)
 
 
@@ -245,6 +249,32 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
                         ctypes.byref(ts), ctypes.c_void_p(workspace.data_ptr()),
                         workspace.numel() * workspace.element_size(), _stream(stream))
     _check(st, "rt3d_trace")
+    out["photons"] = int(photons)
+    return out
+
+
+def trace_noalloc(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int, out: dict, *,
+                  brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
+                  photon_offset: int = 0, accumulate: bool = False, validate: bool = False, max_iters: int = 0,
+                  grid_blocks: int = 0, lds_majorant: int = 0, max_walk: int = 0, pool_photons: int = 0,
+                  refill_lanes: int = 0, merge: bool = True, sobol_entry: bool = False, stream=None) -> dict:
+    """rt3d_trace_noalloc: rt3d_trace with the library's static scratch as
+    workspace; `out` (tallies from alloc_tallies) must be given."""
+    lib = load()
+    for n in ("k_ext", "k_ext_cloud", "ssa", "g", "albedo"):
+        _require_device(getattr(df, n), n, torch.float32)
+    flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
+            (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0)
+    opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, photon_offset, grid_blocks,
+                  lds_majorant=lds_majorant, max_walk=max_walk, pool_photons=pool_photons,
+                  refill_lanes=refill_lanes)
+    gs = grid_struct(df.grid)
+    props = OpticalProps(df.k_ext.data_ptr(), df.k_ext_cloud.data_ptr(), df.ssa.data_ptr(), df.g.data_ptr())
+    ts = tallies_struct(out)
+    st = lib.rt3d_trace_noalloc(ctypes.byref(gs), ctypes.byref(props), ctypes.c_void_p(df.albedo.data_ptr()),
+                                float(sza), float(azimuth), int(photons), int(seed), ctypes.byref(opt),
+                                ctypes.byref(ts), _stream(stream))
+    _check(st, "rt3d_trace_noalloc")
     out["photons"] = int(photons)
     return out
 

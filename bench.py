@@ -26,6 +26,7 @@ import time
 
 import numpy as np
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -419,6 +420,9 @@ def main():
     ap.add_argument("--ttr-reference", type=int, default=TTR_REFERENCE_PER_COLUMN,
                     help="photons per column of the time-to-5 %% reference")
     ap.add_argument("--brick", type=int, default=0, help="cubic brick edge of the headline (0 = default)")
+    ap.add_argument("--budget-s", type=float, default=540.0,
+                    help="wall-clock budget of the whole run: optional legs that would not fit are skipped "
+                         "(and say so) so that the JSON line is always printed")
     ap.add_argument("--inference-only", action="store_true",
                     help="only time denoiser inference on the 1024x1024x128 grid (prints its JSON)")
     ap.add_argument("--probe-only", action="store_true",
@@ -510,24 +514,38 @@ def main():
                          "photons/column on 768x768 columns (different fields)",
     }
     log(f"headline: {res['value']:.3e} events/s, kernel {mean_kms:.1f} ms")
-    if not args.no_secondary:
-        log("access ceiling ...")
-        merged = float(np.clip(ACCESS_ATOMICS_PER_16, 0, 16))
-        res["access_ceiling"] = access_ceiling(g.ncell, tot["collisions"] / args.steps, int(merged), mean_kms)
+    left = lambda: args.budget_s - (time.perf_counter() - T_START)
+    ms_per_photon = mean_kms / max(1, tot["photons"] // args.steps)
     if not args.no_ttr:
-        log("time to 5 % ...")
-        res["time_to_5pct_heating_rms"] = time_to_5pct(tr, args.ttr_reference)
+        # reference + plain sweep (16..4096 per column) + denoised sweep (to 768), in headline-kernel time
+        need = 1e-3 * ms_per_photon * g.ncol * (args.ttr_reference + 5456 + 2624) * 1.15 + 30.0
+        if left() > need + 60.0:
+            log(f"time to 5 % (about {need:.0f} s) ...")
+            res["time_to_5pct_heating_rms"] = time_to_5pct(tr, args.ttr_reference)
+        else:
+            res["time_to_5pct_heating_rms"] = {"skipped": f"needs ~{need:.0f} s, {left():.0f} s of the "
+                                                          f"{args.budget_s:.0f} s budget left"}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        res["cpu_baseline"] = cpu_baseline(tr, counts, res["events_per_photon"])
+        res["cpu_baseline"] = cpu_baseline(tr, counts, res["events_per_photon"],
+                                           target_s=float(np.clip(left() - 120.0, 5.0, 20.0)))
+    if not args.no_secondary and left() > 60.0:
+        log("access ceiling ...")
+        merged = float(np.clip(ACCESS_ATOMICS_PER_16, 0, 16))
+        res["access_ceiling"] = access_ceiling(g.ncell, tot["collisions"] / args.steps, int(merged), mean_kms,
+                                               chains=(1, 2))
     del tr
     torch.cuda.empty_cache()
     if not args.no_secondary:
-        log("secondary legs ...")
-        res["les"] = les_measurement(max(1, min(args.steps, 5)))
-        res["batched_512x512x96"] = batched_measurement(max(1, min(args.steps, 3)))
-        res["two_stream_tod"] = two_stream_measurement()
-        res["denoiser_inference"] = denoiser_measurement()
+        if left() > 90.0:
+            log("secondary legs ...")
+            res["les"] = les_measurement(max(1, min(args.steps, 5)))
+            res["batched_512x512x96"] = batched_measurement(max(1, min(args.steps, 3)))
+            res["two_stream_tod"] = two_stream_measurement()
+            res["denoiser_inference"] = denoiser_measurement()
+        else:
+            res["secondary"] = {"skipped": f"{left():.0f} s of the {args.budget_s:.0f} s budget left"}
+    res["bench_wall_s"] = time.perf_counter() - T_START
     print(json.dumps(res), flush=True)
 
 

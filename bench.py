@@ -370,8 +370,12 @@ def cpu_baseline(tr, counts, gpu_events_per_photon: float, target_s: float = 20.
     """The FP64 C oracle on a bounded sample of the headline workload, on
     every host core: photons of a few g-points drawn with probability
     proportional to their photon shares (each g-point traced on its full
-    1024x1024x128 fields with its own diffuse fraction), sized to about
-    target_s of CPU time."""
+    1024x1024x128 fields with its own diffuse fraction).  A call on these
+    fields has a fixed cost (zeroed 2 GiB tallies, the majorant pass) that
+    would dominate a short sample, so each g-point is traced twice, with a
+    short and a long run, and the rate is the marginal one between them:
+    (events of the long run - events of the short run) / (time difference).
+    The long runs are sized to about target_s of CPU time in total."""
     import oracle
     threads = os.cpu_count() or 1
     m = tr.m
@@ -380,32 +384,39 @@ def cpu_baseline(tr, counts, gpu_events_per_photon: float, target_s: float = 20.
     picks = sorted(set(int(x) for x in rng.choice(m.n_gpoints, size=3, replace=False, p=shares)))
     fdh = tr.fd.cpu().numpy() if tr.fd is not None else np.zeros(m.n_gpoints, np.float32)
     fields = {n: m.fields_of(n) for n in picks}
-    # probe: a small run per g-point, then scale to the time target
-    n0 = 1 << 16
-    t_probe = 0.0
-    for n in picks:
+
+    def run(n, photons, seed):
         t = time.perf_counter()
-        oracle.trace(fields[n], tr.wl.sza, tr.wl.azimuth, n0, 5 + n, brick=tr.brick,
-                     diffuse_fraction=float(fdh[n]), nthreads=threads)
-        t_probe += time.perf_counter() - t
-    per = n0
-    while per < (1 << 24) and t_probe * (2 * per) / n0 < target_s:
-        per *= 2
-    ev, ph, dt = 0, 0, 0.0
-    for n in picks:
-        t = time.perf_counter()
-        r = oracle.trace(fields[n], tr.wl.sza, tr.wl.azimuth, per, 77 + n, brick=tr.brick,
+        r = oracle.trace(fields[n], tr.wl.sza, tr.wl.azimuth, photons, seed, brick=tr.brick,
                          diffuse_fraction=float(fdh[n]), nthreads=threads)
-        dt += time.perf_counter() - t
+        dt = time.perf_counter() - t
         st = dict(zip(oracle.STATS, r["stats"].tolist()))
-        ev += st["collisions"] + st["surface"]
-        ph += per
+        return dt, st["collisions"] + st["surface"]
+
+    n0, n1 = 1 << 16, 1 << 18
+    short, per_photon = {}, 0.0
+    for n in picks:
+        t0, _ = run(n, n0, 5 + n)
+        t1, e1 = run(n, n1, 77 + n)
+        short[n] = (t1, e1)
+        per_photon += max(t1 - t0, 1e-6) / (n1 - n0)
+    per = n1
+    while per < (1 << 24) and per_photon * 2 * per < target_s:
+        per *= 2
+    ev, ph, dt, wall = 0, 0, 0.0, 0.0
+    for n in picks:
+        t2, e2 = run(n, per, 77 + n)
+        ev += e2 - short[n][1]
+        ph += per - n1
+        dt += t2 - short[n][0]
+        wall += t2
     return {"value": ev / dt, "unit": "photon events/s", "cores": threads, "kind": "oracle",
             "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
-            "sample": f"{per} photons in each of g-points {picks} of the {HEADLINE_NAME} workload (drawn by photon "
-                      f"share; full fields, two-stream diffuse fractions; FP64 C oracle, {threads} threads, "
-                      f"{dt:.1f} s, {ev / ph:.1f} events/photon against {gpu_events_per_photon:.1f} for the "
-                      f"GPU's whole g-point mix)",
+            "sample": f"g-points {picks} of the {HEADLINE_NAME} workload (drawn by photon share; full fields, "
+                      f"two-stream diffuse fractions; FP64 C oracle, {threads} threads): marginal rate between "
+                      f"runs of {n1} and {per} photons per g-point ({wall:.1f} s for the long runs, "
+                      f"{dt:.1f} s marginal), {ev / max(ph, 1):.1f} events/photon against "
+                      f"{gpu_events_per_photon:.1f} for the GPU's whole g-point mix",
             "photons_per_s": ph / dt}
 
 

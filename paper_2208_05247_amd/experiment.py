@@ -422,14 +422,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="small grids and few fields (smoke run)")
     ap.add_argument("--out", default=None)
-    ap.add_argument("--train-fields", type=int, default=400)
+    ap.add_argument("--train-fields", type=int, default=800)
     ap.add_argument("--steps-per-field", type=int, default=8)
     ap.add_argument("--sun-entry", action="store_true",
                     help="all photons along the sun beam with the TOA flux weights as g-point shares "
                          "(instead of the two-stream flux at the domain top)")
     ap.add_argument("--config3", action="store_true",
                     help="train/evaluate on 256x256x96 fields (4-photon inputs, 1024-photon targets) instead")
-    ap.add_argument("--target-photons", type=int, default=16384, help="photons per column of training targets")
+    ap.add_argument("--target-photons", type=int, default=32768, help="photons per column of training targets")
+    ap.add_argument("--train-low", default="64,128,192,256,384,512,1024",
+                    help="photons per column of the noisy training inputs (cycled)")
     ap.add_argument("--reference", type=int, default=1 << 17,
                     help="photons per column of the evaluation reference (two halves)")
     ap.add_argument("--save-weights", default=None, help="store the trained weights here (.npz)")
@@ -453,7 +455,8 @@ def main():
         net = dn.Denoiser(base=32, seed=0)
         log(f"denoiser parameters: {net.n_params()}")
         t0 = time.perf_counter()
-        losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz,
+        low = tuple(int(v) for v in args.train_low.split(","))
+        losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz, low=low,
                                high=2048 if args.quick else args.target_photons, tod_entry=not args.sun_entry)
         train_s = time.perf_counter() - t0
         res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,

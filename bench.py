@@ -528,8 +528,8 @@ def main():
     left = lambda: args.budget_s - (time.perf_counter() - T_START)
     ms_per_photon = mean_kms / max(1, tot["photons"] // args.steps)
     if not args.no_ttr:
-        # reference + plain sweep (16..4096 per column) + denoised sweep (to 768), in headline-kernel time
-        need = 1e-3 * ms_per_photon * g.ncol * (args.ttr_reference + 5456 + 2624) * 1.15 + 30.0
+        # reference + plain sweep (16..4096 per column) + denoised sweep (64..1024), in headline-kernel time
+        need = 1e-3 * ms_per_photon * g.ncol * (args.ttr_reference + 5456 + 6016) * 1.15 + 30.0
         if left() > need + 60.0:
             log(f"time to 5 % (about {need:.0f} s) ...")
             res["time_to_5pct_heating_rms"] = time_to_5pct(tr, args.ttr_reference)

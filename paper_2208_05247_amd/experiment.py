@@ -42,13 +42,13 @@ from . import rt3d
 from . import synthetic as syn
 
 # Denoiser weights trained by `python -m paper_2208_05247_amd.experiment
-# --train-fields 800 --target-photons 32768 --save-weights <path> --no-eval`
-# (686 s on one MI355X) on the time-to-5 % configuration (128 x 128 x 128
-# training scenes of 25 x 25 x 20 m cells, two-stream entry); BF16 weights
-# and FP32 biases, identified by the sha256 of their contents (training is
-# bitwise reproducible).
+# --save-weights <path> --no-eval` with the default recipe (800 scenes of
+# 128 x 128 x 128 cells of 25 x 25 x 20 m, two-stream entry, one
+# 32768-photon target and 16 noisy inputs of 128..768 photons per column per
+# scene; 858 s on one MI355X); BF16 weights and FP32 biases, identified by
+# the sha256 of their contents (training is bitwise reproducible).
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "denoiser_25x25x20m.npz")
-WEIGHTS_SHA256 = "061ad6cd2c421ff47e789f7bc839cc9e9dd2ab8a997b8222e89ee7c17df8bd9e"
+WEIGHTS_SHA256 = "bba98230aca74cde41683813c7062c67337b372335ee19d3a53e2fc049a03eef"
 
 F_TOD = 1000.0     # W m^-2, nominal total (direct + diffuse) downward flux at the domain top
 CP = 1004.0        # J kg^-1 K^-1
@@ -172,6 +172,17 @@ def eps_against(h: torch.Tensor, ref_a: torch.Tensor, ref_b: torch.Tensor) -> fl
     return math.sqrt(max(mse, 0.0) / power)
 
 
+def sustained_below(eps, target: float = TARGET_EPS):
+    """Index of the first entry of an increasing sweep from which on every
+    error is at or below the target (None if the last one is above it)."""
+    k = None
+    for i in range(len(eps) - 1, -1, -1):
+        if eps[i] > target:
+            break
+        k = i
+    return k
+
+
 def plain_fit(photons_per_column, eps, kernel_ms, target: float = TARGET_EPS):
     """Plain tracing's time to the target error: eps = a N^-1/2 (the Monte
     Carlo convergence law; a = geometric mean of eps sqrt(N), i.e. least
@@ -286,8 +297,8 @@ def load_committed_denoiser():
 
 
 def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4096),
-             low=(64, 128, 192, 256, 320, 384, 512, 768, 1024), tod_entry: bool = True,
-             tracer: "Tracer" = None, small_ref_per_col: int = 16384, report_through: int = 768):
+             low=(64, 128, 192, 256, 320, 384, 448, 512, 576, 640, 704, 768, 1024), tod_entry: bool = True,
+             tracer: "Tracer" = None, small_ref_per_col: int = 16384, report_through: int = 1024):
     """Plain vs batched+denoised time to a 5 % heating-rate RMS error.
 
     The reference is two independent halves of ref_per_col photons per
@@ -296,8 +307,11 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
     also yields a second, smaller reference (the first parts: the paper's
     16384-photon benchmark size) against which every error is reported as
     well.  Errors have the reference's own noise variance removed.  The
-    denoised sweep stops at the first photon count reaching the target, but
-    not before report_through photons per column."""
+    denoised sweep runs through report_through photons per column.  The
+    denoised time to the target is taken at the smallest photon count from
+    which on every larger count of the sweep stays at or below the target
+    (each count is an independent realisation, so a single lucky dip below
+    it does not count); the first count below it is reported too."""
     tr = tracer if tracer is not None else Tracer(wl, tod_entry=tod_entry)
     g = tr.grid
     half = ref_per_col // 2
@@ -354,8 +368,10 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
             f"trace {rec['trace_ms']:.1f} ms, inference {rec['inference_ms']:.1f} ms")
         if e <= TARGET_EPS and reached is None:
             reached = rec
-        if reached is not None and n >= report_through:
+        if n >= report_through:
             break
+    k = sustained_below([d["eps_denoised"] for d in den], TARGET_EPS)
+    sustained = None if k is None else den[k]
     res = {"plain_fit": {"a": a, "photons_per_column_at_5pct": n5, "t0_ms": t0, "ms_per_unit_N": c,
                          "time_to_5pct_ms": t_plain, "sweep_photons_per_column": list(sweep),
                          "extrapolation_factor": n5 / max(sweep)},
@@ -365,11 +381,17 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
            "reference_relative_noise": noise_ref, "small_reference_photons_per_column": 2 * small_half,
            "small_reference_relative_noise": noise_small, "reference_kernel_ms": ka + kb,
            "entry": "two-stream top of domain" if tod_entry else "sun beam, TOA flux weights", **tr.entry}
-    if reached:
-        t_dn = reached["trace_ms"] + reached["inference_ms"]
+    res["denoised_first_below_target"] = None if reached is None else {
+        "photons_per_column": reached["photons_per_column"],
+        "time_ms": reached["trace_ms"] + reached["inference_ms"]}
+    if sustained:
+        t_dn = sustained["trace_ms"] + sustained["inference_ms"]
+        res["denoised_photons_per_column_at_5pct"] = sustained["photons_per_column"]
         res["denoised_time_to_5pct_ms"] = t_dn
         res["speedup"] = t_plain / t_dn
+        res["speedup_small_reference"] = t_plain_s / t_dn
     else:
+        res["denoised_photons_per_column_at_5pct"] = None
         res["denoised_time_to_5pct_ms"] = None
         res["speedup"] = None
     # what the network gains at equal photons: raw vs denoised error
@@ -423,14 +445,14 @@ def main():
     ap.add_argument("--quick", action="store_true", help="small grids and few fields (smoke run)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--train-fields", type=int, default=800)
-    ap.add_argument("--steps-per-field", type=int, default=8)
+    ap.add_argument("--steps-per-field", type=int, default=16)
     ap.add_argument("--sun-entry", action="store_true",
                     help="all photons along the sun beam with the TOA flux weights as g-point shares "
                          "(instead of the two-stream flux at the domain top)")
     ap.add_argument("--config3", action="store_true",
                     help="train/evaluate on 256x256x96 fields (4-photon inputs, 1024-photon targets) instead")
     ap.add_argument("--target-photons", type=int, default=32768, help="photons per column of training targets")
-    ap.add_argument("--train-low", default="64,128,192,256,384,512,1024",
+    ap.add_argument("--train-low", default="128,192,256,320,384,512,768",
                     help="photons per column of the noisy training inputs (cycled)")
     ap.add_argument("--reference", type=int, default=1 << 17,
                     help="photons per column of the evaluation reference (two halves)")

@@ -64,3 +64,13 @@ def test_multinomial_counts():
     # each count within 6 binomial standard deviations of its mean
     mean = w * (1 << 20)
     assert np.all(np.abs(c1 - mean) < 6 * np.sqrt(mean * (1 - w)))
+
+
+def test_sustained_crossing_ignores_a_lucky_dip():
+    """The denoised time to the target is taken where the error stays below
+    it for every larger photon count of the sweep."""
+    from paper_2208_05247_amd.experiment import sustained_below
+    assert sustained_below([0.09, 0.06, 0.049, 0.053, 0.045, 0.04]) == 4
+    assert sustained_below([0.09, 0.05, 0.049, 0.04]) == 1
+    assert sustained_below([0.09, 0.06, 0.051]) is None
+    assert sustained_below([0.04, 0.03]) == 0

@@ -147,16 +147,22 @@ def test_network_gradients_match_fp64_reference(dn):
     biases = {k: net.bias[k].double().cpu() for k in net.bias}
     rloss, gw, gb, rpred = dr.loss_and_grads(params, biases, feat.double().cpu(), base.double().cpu(),
                                              target.double().cpu())
+    # measured on the MI355X: loss 3.0e-4 relative, predictions 1.2e-3, weight
+    # gradients <= 1.7 % relative with cosine >= 0.99986, bias gradients
+    # <= 1.5 % (e2 is the worst): the difference is the
+    # BF16 storage of activations and gradients between layers
     say("loss gpu", loss.item(), "ref", rloss)
-    assert abs(loss.item() - rloss) <= 2e-2 * rloss
-    assert rel(pred.double().cpu(), rpred) < 2e-2
+    assert abs(loss.item() - rloss) <= 1e-3 * rloss
+    pe = rel(pred.double().cpu(), rpred)
+    say("prediction rel err", round(pe, 6))
+    assert pe < 5e-3
     for k in dr.ORDER:
         e = rel(net.g[k].double().cpu(), gw[k])
         cos = float((net.g[k].double().cpu() * gw[k]).sum() / (net.g[k].double().cpu().norm() * gw[k].norm()))
-        say("grad", k, "rel err", round(e, 5), "cos", round(cos, 6))
-        assert e < 6e-2 and cos > 0.998, k
         eb = rel(net.gbias[k].double().cpu(), gb[k])
-        assert eb < 6e-2, (k, "bias", eb)
+        say("grad", k, "rel err", round(e, 5), "cos", round(cos, 6), "bias rel err", round(eb, 5))
+        assert e < 3e-2 and cos > 0.9995, k
+        assert eb < 3e-2, (k, "bias", eb)
 
 
 def test_training_reduces_loss(dn):

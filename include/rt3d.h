@@ -91,7 +91,7 @@
 extern "C" {
 #endif
 
-#define RT3D_ABI_VERSION 2
+#define RT3D_ABI_VERSION 3
 
 typedef enum {
     RT3D_OK = 0,
@@ -219,6 +219,17 @@ typedef struct {
     int32_t refill_lanes;    /* a wave starts new photons once at least this
                                 many of its 64 lanes are idle (or none is
                                 alive), 1..64; 0 = 16 */
+    int32_t tile_x, tile_y;  /* entry tile of the photon schedule in columns
+                                (see rt3d_schedule_slots): the work queue
+                                hands out the photons of all full passes
+                                tile by tile, so the photons in flight at one
+                                time enter a few neighbouring tiles; each must
+                                divide nx (ny).  0 = automatic: tiles whose
+                                columns hold about 128 MiB of cell records and
+                                heating tallies (nz * 32 bytes per column),
+                                close to square (edges: divisors of nx, ny),
+                                or the whole domain when it holds less.  Order
+                                only: results do not depend on it. */
 } rt3d_options;
 
 /* Several g-points in one launch (sec. 2.2: 112 shortwave quadrature points;
@@ -371,6 +382,26 @@ rt3d_status rt3d_philox4x32_10(const uint32_t* ctr, uint64_t seed,
  * uses their first 24 digits.  p is taken mod 2^32. */
 rt3d_status rt3d_sobol_entry(uint64_t first_pass, uint32_t n, uint64_t column,
                              uint64_t seed, uint32_t* out, void* stream);
+
+/* The photon schedule of a trace call, evaluated on the HOST (no device
+ * work), for tests and inspection.  The work queue of rt3d_trace /
+ * rt3d_trace_batched hands out slots 0 .. total-1 (total = sum of photons[]);
+ * slot s is traced as photon id of g-point gp, entering column col (both
+ * independent of the schedule: photon k of g-point n has id =
+ * photon_offset + k and enters column (id + o_n) mod (nx*ny)).  With
+ * P_n = photons[n] div (nx*ny), slots first cover the P_n full passes of
+ * every g-point tile by tile (tiles of opt->tile_x x opt->tile_y columns,
+ * row-major; inside a tile pass by pass, g-point by g-point, the tile's
+ * columns row-major), then the photons left over, g-point by g-point in
+ * order of k.  col_offset: o_n per g-point (host uint64 [n_gpoints]; the
+ * tracer draws them from Philox, the hook takes any values in [0, nx*ny)).
+ * For slots first_slot .. first_slot+n-1 writes gp_out[i], id_out[i],
+ * col_out[i] (host arrays [n]).  RT3D_EINVAL for a bad grid or options, a
+ * tile not dividing the grid, offsets out of range or slots beyond total. */
+rt3d_status rt3d_schedule_slots(const rt3d_grid* grid, int32_t n_gpoints, const uint64_t* photons,
+                                const uint64_t* col_offset, const rt3d_options* opt,
+                                uint64_t first_slot, uint64_t n, int32_t* gp_out,
+                                uint64_t* id_out, uint32_t* col_out);
 
 /* The tracer's scattering samplers, element-wise, for tests (sec. 2.3,
  * phase-function paragraph).  kind 0: Henyey-Greenstein cosine of the

@@ -2,8 +2,10 @@
 
 Picks the acceleration-grid cell ("brick") shape, the crossings a lane makes
 per loop iteration, the persistent grid size, the photon-id pool a wave takes
-per refill, how many idle lanes a wave waits for before it starts new photons
-and the tally-merging mode from short calibration runs.  The
+per refill, how many idle lanes a wave waits for before it starts new photons,
+the tally-merging mode and the entry tile of the photon schedule from short
+calibration runs (the tile matters only when the sample holds full passes
+over the columns, i.e. at least as many photons per g-point as columns).  The
 objective is tracing-kernel time per photon (HIP events around the kernel),
 not events/s: looser majorants inflate the event count without doing more
 useful work.  Every candidate traces the same photons through the same
@@ -31,6 +33,7 @@ BRICKS = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (8, 8, 4), (8, 8, 16), (4, 4, 8), 
 WALKS = [0, 1, 2, 4, 8]
 POOLS = [64, 256, 1024]
 REFILLS = [1, 4, 8, 16, 32]
+TILES = [(16, 16), (32, 32), (128, 128), (256, 256), "domain"]  # automatic: 64 x 64 (largest divisor <= 64)
 
 
 @dataclasses.dataclass
@@ -77,7 +80,7 @@ def _store_cache(path, cache):
 
 
 def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=None, pools=None,
-            grid_mults=(1,), try_merge=True, refills=None):
+            grid_mults=(1,), try_merge=True, refills=None, tiles=None):
     """Staged coordinate search; run(opts) returns kernel ms for `sample` photons."""
     table = []
 
@@ -124,6 +127,14 @@ def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=
             best_ms, best = ms, o
     if try_merge:
         o = {**best, "merge": False}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
+    for t in (tiles or TILES):
+        t = (grid.nx, grid.ny) if t == "domain" else t
+        if grid.nx % t[0] or grid.ny % t[1]:
+            continue
+        o = {**best, "tile": tuple(t)}
         ms = measure(o)
         if ms < best_ms:
             best_ms, best = ms, o

@@ -102,12 +102,13 @@ class Tracer:
     (shares and diffuse fraction per g-point), else all along the sun beam
     with the TOA flux weights as shares."""
 
-    def __init__(self, wl: "syn.BatchedWorkload", brick=(8, 8, 8), tod_entry: bool = True):
+    def __init__(self, wl: "syn.BatchedWorkload", brick=(8, 8, 8), tod_entry: bool = True, tile=(0, 0)):
         self.wl = wl
         self.m = wl.medium
         self.grid = self.m.grid
         self.dm = rt3d.DeviceBatchedMedium.from_host(self.m)
         self.brick = brick
+        self.tile = tuple(tile)  # entry tile of the photon schedule (speed only)
         if tod_entry:
             self.shares, self.fd, self.entry = top_of_domain_entry(wl)
         else:
@@ -149,7 +150,7 @@ class Tracer:
             counts = multinomial_counts(self.shares, part, seed + 1000 * k)
             raw = rt3d.trace_batched(self.dm, self.wl.sza, self.wl.azimuth, counts, seed + 1000 * k,
                                      brick=self.brick, out=self.out, workspace=self.ws, timed=True,
-                                     accumulate=k > 0, gpoint_diffuse=self.fd)
+                                     accumulate=k > 0, gpoint_diffuse=self.fd, tile=self.tile)
             kms += rt3d.last_trace_ms()
         fin = rt3d.finalize(self.grid, raw, total, layer_scale=self.ls)
         return fin["abs_dir"], fin["abs_dif"], kms, total

@@ -31,7 +31,7 @@ EXPORTS = ("rt3d_abi_version", "rt3d_status_string", "rt3d_last_device_error",
            "rt3d_default_options", "rt3d_workspace_size", "rt3d_majorant_build",
            "rt3d_trace", "rt3d_last_trace_ms", "rt3d_finalize", "rt3d_philox4x32_10",
            "rt3d_workspace_size_batched", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream",
-           "rt3d_phase_sample", "rt3d_turn", "rt3d_trace_noalloc")
+           "rt3d_phase_sample", "rt3d_turn", "rt3d_trace_noalloc", "rt3d_schedule_slots")
 MAX_GPOINTS = 256
 
 
@@ -62,7 +62,7 @@ class Options(ctypes.Structure):
                 ("photon_offset", ctypes.c_uint64), ("grid_blocks", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("lds_majorant", ctypes.c_int32),
                 ("max_walk", ctypes.c_int32), ("pool_photons", ctypes.c_int32),
-                ("refill_lanes", ctypes.c_int32)]
+                ("refill_lanes", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32)]
 
 
 class BatchedMedium(ctypes.Structure):
@@ -113,11 +113,13 @@ def load(path: str = LIB_PATH):
                                     ctypes.c_int32, P, P, P]
     lib.rt3d_phase_sample.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_uint32, P]
     lib.rt3d_turn.argtypes = [P, P, P, P, ctypes.c_uint32, P]
+    lib.rt3d_schedule_slots.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, P, P, ctypes.POINTER(Options),
+                                        ctypes.c_uint64, ctypes.c_uint64, P, P, P]
     for name in ("rt3d_majorant_build", "rt3d_trace", "rt3d_trace_noalloc", "rt3d_last_trace_ms", "rt3d_finalize",
                  "rt3d_philox4x32_10", "rt3d_trace_batched", "rt3d_sobol_entry", "rt3d_two_stream",
-                 "rt3d_phase_sample", "rt3d_turn", "rt3d_trace_noalloc"):
+                 "rt3d_phase_sample", "rt3d_turn", "rt3d_trace_noalloc", "rt3d_schedule_slots"):
         getattr(lib, name).restype = ctypes.c_int
-    if lib.rt3d_abi_version() != 2:
+    if lib.rt3d_abi_version() != 3:
         raise RuntimeError("librt3d.so ABI version mismatch")
     _lib = lib
     return lib
@@ -174,7 +176,7 @@ class DeviceFields:
 
 def options(brick=(8, 8, 8), diffuse_fraction=0.0, rr_threshold=0.5, flags=0, max_iters=0,
             photon_offset=0, grid_blocks=0, block_threads=0, lds_majorant=0, max_walk=0,
-            pool_photons=0, refill_lanes=0) -> Options:
+            pool_photons=0, refill_lanes=0, tile=(0, 0)) -> Options:
     o = Options()
     load().rt3d_default_options(ctypes.byref(o))
     o.brick_x, o.brick_y, o.brick_z = (int(b) for b in brick)
@@ -189,7 +191,27 @@ def options(brick=(8, 8, 8), diffuse_fraction=0.0, rr_threshold=0.5, flags=0, ma
     o.max_walk = int(max_walk)
     o.pool_photons = int(pool_photons)
     o.refill_lanes = int(refill_lanes)
+    o.tile_x, o.tile_y = (int(t) for t in tile)
     return o
+
+
+def schedule_slots(grid, photons, col_offsets, opt: Options, first_slot: int = 0, n: int | None = None):
+    """Host evaluation of the photon schedule (rt3d_schedule_slots): for work
+    queue slots first_slot .. first_slot+n-1 the g-point, photon id and entry
+    column each slot is traced as.  No device work."""
+    counts = np.ascontiguousarray(photons, dtype=np.uint64)
+    offs = np.ascontiguousarray(col_offsets, dtype=np.uint64)
+    if counts.ndim != 1 or offs.shape != counts.shape or not 1 <= counts.size <= MAX_GPOINTS:
+        raise ValueError("photons and col_offsets must be 1-D of equal length 1..256")
+    if n is None:
+        n = int(counts.sum()) - int(first_slot)
+    gp = np.empty(n, np.int32)
+    ids = np.empty(n, np.uint64)
+    cols = np.empty(n, np.uint32)
+    _check(load().rt3d_schedule_slots(ctypes.byref(grid_struct(grid)), counts.size, counts.ctypes.data,
+                                      offs.ctypes.data, ctypes.byref(opt), int(first_slot), int(n),
+                                      gp.ctypes.data, ids.ctypes.data, cols.ctypes.data), "rt3d_schedule_slots")
+    return gp, ids, cols
 
 
 def workspace_size(grid, opt: Options) -> int:
@@ -224,7 +246,7 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
           photon_offset: int = 0, accumulate: bool = False, validate: bool = False, timed: bool = False,
           max_iters: int = 0, grid_blocks: int = 0, lds_majorant: int = 0, max_walk: int = 0,
           pool_photons: int = 0, refill_lanes: int = 0, merge: bool = True, sobol_entry: bool = False,
-          out: Optional[dict] = None,
+          tile=(0, 0), out: Optional[dict] = None,
           workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
     """rt3d_trace: raw uint64 tallies (int64 tensors) of `photons` photons."""
     lib = load()
@@ -235,7 +257,7 @@ def trace(df: DeviceFields, sza: float, azimuth: float, photons: int, seed: int,
             (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, photon_offset, grid_blocks,
                   lds_majorant=lds_majorant, max_walk=max_walk, pool_photons=pool_photons,
-                  refill_lanes=refill_lanes)
+                  refill_lanes=refill_lanes, tile=tile)
     gs = grid_struct(grid)
     nws = workspace_size(grid, opt)
     if workspace is None:
@@ -257,7 +279,8 @@ def trace_noalloc(df: DeviceFields, sza: float, azimuth: float, photons: int, se
                   brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
                   photon_offset: int = 0, accumulate: bool = False, validate: bool = False, max_iters: int = 0,
                   grid_blocks: int = 0, lds_majorant: int = 0, max_walk: int = 0, pool_photons: int = 0,
-                  refill_lanes: int = 0, merge: bool = True, sobol_entry: bool = False, stream=None) -> dict:
+                  refill_lanes: int = 0, merge: bool = True, sobol_entry: bool = False, tile=(0, 0),
+                  stream=None) -> dict:
     """rt3d_trace_noalloc: rt3d_trace with the library's static scratch as
     workspace; `out` (tallies from alloc_tallies) must be given."""
     lib = load()
@@ -267,7 +290,7 @@ def trace_noalloc(df: DeviceFields, sza: float, azimuth: float, photons: int, se
             (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, photon_offset, grid_blocks,
                   lds_majorant=lds_majorant, max_walk=max_walk, pool_photons=pool_photons,
-                  refill_lanes=refill_lanes)
+                  refill_lanes=refill_lanes, tile=tile)
     gs = grid_struct(df.grid)
     props = OpticalProps(df.k_ext.data_ptr(), df.k_ext_cloud.data_ptr(), df.ssa.data_ptr(), df.g.data_ptr())
     ts = tallies_struct(out)
@@ -314,7 +337,7 @@ def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: 
                   brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
                   accumulate: bool = False, validate: bool = False, timed: bool = False, max_iters: int = 0,
                   grid_blocks: int = 0, max_walk: int = 0, pool_photons: int = 0, refill_lanes: int = 0,
-                  merge: bool = True,
+                  merge: bool = True, tile=(0, 0),
                   sobol_entry: bool = False, gpoint_diffuse: Optional[torch.Tensor] = None,
                   out: Optional[dict] = None, workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
     """rt3d_trace_batched: broadband raw tallies of all g-points in one launch.
@@ -334,7 +357,7 @@ def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: 
     flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
             (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, 0, grid_blocks, max_walk=max_walk,
-                  pool_photons=pool_photons, refill_lanes=refill_lanes)
+                  pool_photons=pool_photons, refill_lanes=refill_lanes, tile=tile)
     gs = grid_struct(grid)
     nws = workspace_size_batched(grid, ngp, opt)
     if workspace is None:

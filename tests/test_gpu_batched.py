@@ -80,7 +80,8 @@ def test_batched_equals_sum_of_single_gpoints(rt3d):
 
 @pytest.mark.parametrize("kw", [dict(max_walk=1), dict(max_walk=3), dict(pool_photons=64),
                                 dict(pool_photons=1024), dict(merge=False), dict(grid_blocks=5),
-                                dict(refill_lanes=1), dict(refill_lanes=64), dict(refill_lanes=7)])
+                                dict(refill_lanes=1), dict(refill_lanes=64), dict(refill_lanes=7),
+                                dict(tile=(8, 8)), dict(tile=(4, 16)), dict(tile=(32, 1)), dict(tile=(1, 1))])
 def test_launch_options_do_not_change_tallies(rt3d, kw):
     wl = syn.small_cumulus()
     df = rt3d.DeviceFields.from_host(wl.fields)
@@ -97,6 +98,33 @@ def test_launch_options_do_not_change_tallies(rt3d, kw):
     b1 = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 9, brick=bw.brick, **kw))
     for k in ARRAYS + ("ledger", "stats"):
         assert np.array_equal(b0[k], b1[k]), (k, "batched", kw)
+
+
+def test_schedule_tiles_do_not_change_tallies(rt3d):
+    """The photon schedule (entry tiles of the work queue) only reorders:
+    uneven g-point counts (full passes plus a remainder, none, fewer photons
+    than columns) and a single-g-point run with a photon offset give the
+    same uint64 tallies, ledger and counters for every tile."""
+    bw = small_batch(n_gp=6, photons=1 << 16, seed=11)
+    dm = rt3d.DeviceBatchedMedium.from_host(bw.medium)
+    ncol = bw.medium.grid.nx * bw.medium.grid.ny
+    counts = [5 * ncol + 333, 0, 300, 3 * ncol, 17, 2 * ncol + ncol - 1]
+    ref = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, counts, 21, brick=bw.brick, tile=(32, 32)))
+    ledger_ok(ref, sum(counts))
+    for t in [(0, 0), (8, 8), (16, 4), (1, 32), (2, 2)]:
+        got = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, counts, 21, brick=bw.brick, tile=t))
+        for k in ARRAYS + ("ledger", "stats"):
+            assert np.array_equal(ref[k], got[k]), (k, t)
+    wl = syn.small_cumulus()
+    df = rt3d.DeviceFields.from_host(wl.fields)
+    n, off = 7 * 1024 + 500, 123_456_789
+    ref = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, n, 5, brick=wl.brick, photon_offset=off, tile=(32, 32)))
+    for t in [(4, 4), (16, 2), (1, 1)]:
+        got = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, n, 5, brick=wl.brick, photon_offset=off, tile=t))
+        for k in ARRAYS + ("ledger", "stats"):
+            assert np.array_equal(ref[k], got[k]), (k, "offset", t)
+    with pytest.raises(rt3d.Rt3dError):
+        rt3d.trace(df, wl.sza, wl.azimuth, n, 5, brick=wl.brick, tile=(3, 4))
 
 
 def test_batched_parity_vs_oracle(rt3d):

@@ -64,7 +64,7 @@ def test_every_header_is_exported_by_its_library(header):
 
 
 def test_abi_and_strings(lib):
-    assert lib.rt3d_abi_version() == 2
+    assert lib.rt3d_abi_version() == 3
     for s in range(4):
         assert lib.rt3d_status_string(s)
     assert lib.rt3d_status_string(99) == b"unknown status"
@@ -85,10 +85,11 @@ def test_workspace_size_host_only(lib):
     g = Grid(256, 256, 128, 50.0, 50.0, 25.0)
     o = rt3d.options(brick=(8, 8, 8))
     n = rt3d.workspace_size(g, o)
-    # control block, photon ranges + column offsets, majorants, packed cells
+    # control block, schedule tables (pass and remainder prefix sums, column
+    # offsets), majorants, packed cells
     assert n == 256 + 256 + 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16
     nb = rt3d.workspace_size_batched(g, 112, o)
-    meta = (8 * (2 * 112 + 1) + 255) // 256 * 256
+    meta = (8 * (3 * 112 + 2) + 255) // 256 * 256
     assert nb == 256 + meta + 112 * 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16 + 112 * 128 * 8 + 128 * 32 * 32 * 4
     assert lib.rt3d_workspace_size_batched(ctypes.byref(rt3d.grid_struct(g)), 0, ctypes.byref(o)) == 0
     assert lib.rt3d_workspace_size_batched(ctypes.byref(rt3d.grid_struct(g)), 257, ctypes.byref(o)) == 0

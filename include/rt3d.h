@@ -194,6 +194,12 @@ enum {
                                      initialisation paragraph) instead of
                                      independent uniforms; see
                                      rt3d_sobol_entry for the definition */
+#define RT3D_FLAG_WAVE_AGGREGATE 0x20u /* wave-aggregated tally atomics: lanes of
+                                     a wavefront that update the same tally
+                                     element in the same instruction add
+                                     their values first and one atomic is
+                                     issued per distinct element (same
+                                     results; speed only) */
 
 typedef struct {
     /* acceleration-grid cell ("brick") in fine cells; must divide nx, ny, nz */

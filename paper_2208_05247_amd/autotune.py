@@ -3,7 +3,8 @@
 Picks the acceleration-grid cell ("brick") shape, the crossings a lane makes
 per loop iteration, the persistent grid size, the photon-id pool a wave takes
 per refill, how many idle lanes a wave waits for before it starts new photons,
-the tally-merging mode and the entry tile of the photon schedule from short
+the tally mode (merging a lane's deposits, wave-aggregated atomics) and the
+entry tile of the photon schedule from short
 calibration runs (the tile matters only when the sample holds full passes
 over the columns, i.e. at least as many photons per g-point as columns).  The
 objective is tracing-kernel time per photon (HIP events around the kernel),
@@ -126,10 +127,10 @@ def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=
         if ms < best_ms:
             best_ms, best = ms, o
     if try_merge:
-        o = {**best, "merge": False}
-        ms = measure(o)
-        if ms < best_ms:
-            best_ms, best = ms, o
+        for o in ({**best, "merge": False}, {**best, "wave_aggregate": True}):
+            ms = measure(o)
+            if ms < best_ms:
+                best_ms, best = ms, o
     for t in (tiles or TILES):
         t = (grid.nx, grid.ny) if t == "domain" else t
         if grid.nx % t[0] or grid.ny % t[1]:

@@ -280,6 +280,7 @@ struct TraceParams {
     uint32_t pool;   // photon ids a wave takes from the queue at a time
     uint32_t refill; // a wave refills once this many of its lanes are idle
     int merge;       // merge consecutive deposits of a lane into one cell
+    int wave_agg;    // wave-aggregated tally atomics (same address, same instruction)
     int nx, ny, nz, bx, by, bz, mx, my, mz;
     float dx, dy, dz, inv_dx, inv_dy, inv_dz;
     float cx, cy, cz;  // acceleration-grid cell size in metres
@@ -300,6 +301,33 @@ enum { S_PHOT, S_COLL, S_NULL, S_GAS, S_CLOUD, S_SFC, S_ESC, S_RR_KILL, S_RR_SUR
 
 __device__ __forceinline__ void lds_add(unsigned long long* a, unsigned long long v) {
     if (v) atomicAdd(a, v);
+}
+
+// Tally update.  agg = 0: one atomic per lane.  agg = 1 (wave-aggregated):
+// the lanes that update the same address in this instruction add their
+// values first and one of them issues the atomic; the loop visits each
+// distinct address of the active lanes once (scalar, wave-uniform).
+__device__ __forceinline__ void tally_add(unsigned long long* p, unsigned long long v, int agg) {
+    if (!agg) {
+        atomicAdd(p, v);
+        return;
+    }
+    uint64_t todo = __ballot(1);
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const uint64_t al = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a >> 32), l) << 32) |
+                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a, l);
+        const uint64_t m = __ballot(a == al);
+        unsigned long long sum = 0;
+        for (uint64_t mm = m; mm; mm &= mm - 1) {
+            const int j = __ffsll((unsigned long long)mm) - 1;
+            sum += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j) << 32) |
+                   (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+        }
+        if ((int)__lane_id() == l) atomicAdd(p, sum);
+        todo &= ~m;
+    }
 }
 
 __device__ __forceinline__ uint64_t lane_mask_lt() {
@@ -396,7 +424,7 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
     auto flush_deposit = [&]() {
         if (pend_amt) {
             const uint32_t cell = pend_key & 0x7fffffffu;
-            atomicAdd(pend_key & 0x80000000u ? &P.abs_dif[cell] : &P.abs_dir[cell], pend_amt);
+            tally_add(pend_key & 0x80000000u ? &P.abs_dif[cell] : &P.abs_dir[cell], pend_amt, P.wave_agg);
         }
         pend_key = kNoCell;
         pend_amt = 0;
@@ -647,10 +675,10 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             const int i = cell_ix(px, P.inv_dx, bi, P.bx);
             const int j = cell_ix(py, P.inv_dy, bj, P.by);
             const int c2 = j * P.nx + i;
-            atomicAdd(direct ? &P.sfc_dir[c2] : &P.sfc_dif[c2], (unsigned long long)w);
+            tally_add(direct ? &P.sfc_dir[c2] : &P.sfc_dif[c2], (unsigned long long)w, P.wave_agg);
             const uint32_t wn = min(w, (uint32_t)rintf(P.albedo[c2] * (float)w));
             if (w != wn) {
-                atomicAdd(&P.sfc_abs[c2], (unsigned long long)(w - wn));
+                tally_add(&P.sfc_abs[c2], (unsigned long long)(w - wn), P.wave_agg);
                 lds_add(&s_ledger[L_SFC], w - wn);
             }
             atomicAdd(&s_stats[S_SFC], 1ull);
@@ -676,7 +704,7 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             // ---- leaves through the top of the domain
             const int i = cell_ix(px, P.inv_dx, bi, P.bx);
             const int j = cell_ix(py, P.inv_dy, bj, P.by);
-            atomicAdd(&P.toa_up[j * P.nx + i], (unsigned long long)w);
+            tally_add(&P.toa_up[j * P.nx + i], (unsigned long long)w, P.wave_agg);
             lds_add(&s_ledger[L_TOA], w);
             atomicAdd(&s_stats[S_ESC], 1ull);
             finish_photon();
@@ -1228,6 +1256,7 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
     P.pool = o.pool_photons > 0 ? (uint32_t)o.pool_photons : 256u;
     P.refill = o.refill_lanes > 0 ? (uint32_t)o.refill_lanes : 16u;
     P.merge = (o.flags & RT3D_FLAG_NO_MERGE) ? 0 : 1;
+    P.wave_agg = (o.flags & RT3D_FLAG_WAVE_AGGREGATE) ? 1 : 0;
     P.sobol = (o.flags & RT3D_FLAG_SOBOL_ENTRY) ? 1 : 0;
     P.seed = seed;
     P.photons = total;

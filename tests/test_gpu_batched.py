@@ -3,7 +3,8 @@ launch options the autotuner varies.
 
 Bitwise: one batched launch equals the sum of single-g-point batched
 launches (keys seed + n); every launch option (crossings per iteration,
-LDS staging, photon pool, tally merging, grid size) leaves the uint64
+LDS staging, photon pool, tally merging, wave-aggregated atomics, grid
+size, schedule tile) leaves the uint64
 tallies unchanged.  Statistical: the broadband tallies agree with the FP64
 oracle run per g-point on the materialised fields and summed."""
 import sys
@@ -81,7 +82,8 @@ def test_batched_equals_sum_of_single_gpoints(rt3d):
 @pytest.mark.parametrize("kw", [dict(max_walk=1), dict(max_walk=3), dict(pool_photons=64),
                                 dict(pool_photons=1024), dict(merge=False), dict(grid_blocks=5),
                                 dict(refill_lanes=1), dict(refill_lanes=64), dict(refill_lanes=7),
-                                dict(tile=(8, 8)), dict(tile=(4, 16)), dict(tile=(32, 1)), dict(tile=(1, 1))])
+                                dict(tile=(8, 8)), dict(tile=(4, 16)), dict(tile=(32, 1)), dict(tile=(1, 1)),
+                                dict(wave_aggregate=True), dict(wave_aggregate=True, merge=False)])
 def test_launch_options_do_not_change_tallies(rt3d, kw):
     wl = syn.small_cumulus()
     df = rt3d.DeviceFields.from_host(wl.fields)

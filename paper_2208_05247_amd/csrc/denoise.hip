@@ -145,9 +145,9 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const ConvArgs a) {
 // Tiled 3x3x3 convolution.  A workgroup (4 waves) owns an output tile of
 // kZ z-slices x kTY y-rows x kTX x-voxels and a slab of up to 64 output
 // channels.  For each 16-channel input chunk the
-// ((kZ+2) x (kTY+2) x (kTX+2))-voxel input halo is staged in LDS once (zero
-// outside the domain), so a staged plane serves kZ output planes; every
-// wave then runs the 27 taps over its 2 rows x 2 cout tiles in each output
+// ((kZ+2) x (kTY+2) x (kTX+2))-voxel input halo is loaded straight into LDS
+// once (zero outside the domain), so a staged plane serves kZ output planes;
+// every wave then runs the 27 taps over its 2 rows x 2 cout tiles in each output
 // plane: A fragments are contiguous 1 KiB rows of the staged halo, B
 // fragments (weights) come from global memory, where the small weight
 // tensor stays cache resident, one tap ahead of their use, and each is used
@@ -158,43 +158,42 @@ constexpr int kHaloVox = (kZ + 2) * kHaloY * kHaloX;
 
 // Stages the input halo of one 16-channel chunk, planes z0-1 .. z0+NZ and
 // rows y0-1 .. y0+HY-2 of columns x0-1 .. x0+kTX, into LDS as two 16-byte
-// halves per voxel (zero outside the domain), with NT threads.  Every load
-// address is clamped into the domain and the zero is selected afterwards,
-// so the loop is straight-line code and a batch of SB loads per thread is
-// in flight at once (a guarded load per iteration would wait for each).
-template <int NZ, int HY, int NT, int SB>
-__device__ __forceinline__ void stage_halo16(uint4* tile, const ConvArgs& a, int c0, int x0, int y0, int z0) {
-    constexpr int kSlots = NZ * HY * kHaloX * 2, kPer = (kSlots + NT - 1) / NT;
+// halves per voxel (slot 2 v + part), with NT threads.  The loads go
+// straight to LDS (global_load_lds_dwordx4: lane l of a wave writes its 16
+// bytes at the wave's LDS base + 16 l, checked on the device), so no
+// registers hold the data and all of a chunk's loads are in flight at once.
+// Slots are filled in batches of 64, one wave instruction each; the tile
+// holds a whole number of batches (tile_slots), and slots outside the domain
+// or past the halo read the 16-byte zero block.  The caller waits for the
+// loads (vmcnt) before the barrier that publishes the tile.
+constexpr int tile_slots(int halo_vox) { return (halo_vox * 2 + 63) / 64 * 64; }
+
+template <int NZ, int HY, int NT>
+__device__ __forceinline__ void stage_halo16_lds(uint4* tile, const ConvArgs& a, int c0, int x0, int y0, int z0) {
+    constexpr int kSlots = NZ * HY * kHaloX * 2, kBatches = (kSlots + 63) / 64, kWaves = NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool from1 = c0 < a.c1;
     const uint16_t* base = from1 ? a.x1 + c0 : a.x2 + (c0 - a.c1);
     const long cs = from1 ? a.c1 : a.c2;
     const bool half_res = from1 && a.up1;
-#pragma unroll 1
-    for (int j0 = 0; j0 < kPer; j0 += SB) {  // not unrolled: keeps the address math out of the chunk loop's registers
-        uint4 v[SB];
-#pragma unroll
-        for (int j = 0; j < SB; ++j) {
-            const int i = threadIdx.x + NT * (j0 + j);
-            const int vx = i >> 1, part = i & 1;
-            const int hx = vx % kHaloX, hy = (vx / kHaloX) % HY, hz = vx / (kHaloX * HY);
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            const bool in = x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D;
-            const int xc = min(max(x, 0), a.W - 1), yc = min(max(y, 0), a.H - 1), zc = min(max(z, 0), a.D - 1);
-            const long vox = half_res ? ((long)(zc >> 1) * (a.H >> 1) + (yc >> 1)) * (a.W >> 1) + (xc >> 1)
-                                      : ((long)zc * a.H + yc) * a.W + xc;
-            const uint4 ld = *(const uint4*)(base + vox * cs + 8 * part);
-            v[j] = in ? ld : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int j = 0; j < SB; ++j) {
-            const int i = threadIdx.x + NT * (j0 + j);
-            if (j0 + j < kPer && i < kSlots) tile[i] = v[j];
-        }
+    for (int bt = wave; bt < kBatches; bt += kWaves) {
+        const int i = bt * 64 + lane;
+        const int vx = i >> 1, part = i & 1;
+        const int hx = vx % kHaloX, hy = (vx / kHaloX) % HY, hz = vx / (kHaloX * HY);
+        const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+        const bool in = i < kSlots && x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D;
+        const long vox = half_res ? ((long)(z >> 1) * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1)
+                                  : ((long)z * a.H + y) * a.W + x;
+        const uint16_t* src = in ? base + vox * cs + 8 * part : reinterpret_cast<const uint16_t*>(dn_zero16);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(tile + bt * 64), 16, 0, 0);
     }
 }
 
+__device__ __forceinline__ void wait_loads() { __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_tiled_kernel(const ConvArgs a) {
-    __shared__ uint4 tile[kHaloVox * 2];  // 16 channels = two 16-byte halves per voxel
+    __shared__ uint4 tile[tile_slots(kHaloVox)];  // 16 channels = two 16-byte halves per voxel
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, half = lane >> 5;
     const int nslab = (a.cout + 63) / 64;
@@ -237,7 +236,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
     load_b(0, 0, bv);
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();  // the previous chunk's halo is no longer read
-        stage_halo16<kZ + 2, kHaloY, 256, 4>(tile, a, c0, x0, y0, z0);
+        stage_halo16_lds<kZ + 2, kHaloY, 256>(tile, a, c0, x0, y0, z0);
+        wait_loads();
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
@@ -313,7 +313,7 @@ constexpr int kHaloVox32 = (kZ32 + 2) * kHaloY32 * kHaloX;
 static_assert(4 * kZ32 * 4 * 32 * 32 * 2 <= kHaloVox32 * 2 * 16, "head scratch exceeds the halo tile");
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_c32_kernel(const ConvArgs a) {
-    __shared__ uint4 tile[kHaloVox32 * 2];
+    __shared__ uint4 tile[tile_slots(kHaloVox32)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, half = lane >> 5;
     const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY32 - 1) / kTY32;
@@ -335,7 +335,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
 
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();
-        stage_halo16<kZ32 + 2, kHaloY32, 256, 4>(tile, a, c0, x0, y0, z0);
+        stage_halo16_lds<kZ32 + 2, kHaloY32, 256>(tile, a, c0, x0, y0, z0);
+        wait_loads();
         __syncthreads();
         for (int dz = 0; dz < 3; ++dz) {
             // the 9 weight fragments of this z-slice of the kernel

@@ -39,6 +39,7 @@ namespace {
 
 constexpr uint32_t kWOne = 0x80000000u;  // weight one in units of 2^-31
 constexpr uint32_t kNoCell = 0xffffffffu;
+constexpr uint32_t kNoMajorant = 0x7fffffffu;  // a NaN: never a majorant (those are >= 0, or negated as a flag)
 constexpr size_t kLdsMajorantBytes = 64 * 1024;  // automatic LDS staging limit (two workgroups per CU)
 
 // ---------------------------------------------------------------------------
@@ -406,6 +407,10 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
     float px = 0.f, py = 0.f, pz = 0.f, ux = 0.f, uy = 0.f, uz = -1.f;
     int bi = 0, bj = 0, bk = 0;
     float tau = -1.f;  // optical depth left on the current free path; < 0: draw a new one
+    // majorant of the current acceleration cell once read (kNoMajorant: not
+    // yet); a photon stays in its cell across the null collisions there, so
+    // the walk re-reads it only after a crossing or a new emission
+    float kmaj = __uint_as_float(kNoMajorant);
     uint32_t w = 0, step = 0, iters = 0;
     bool direct = false;
     // merged deposit: cell index, bit 31 set for diffuse
@@ -526,6 +531,7 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
                     bi = ic / P.bx;
                     bj = jc / P.by;
                     bk = P.mz - 1;
+                    kmaj = __uint_as_float(kNoMajorant);
                     w = kWOne;
                     step = 0;
                     iters = 0;
@@ -561,7 +567,9 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             if (walked >= P.max_walk) { outcome = kWalking; break; }
             ++iters;
             // factored majorants carry the brick's "no cloud" flag in the sign bit
-            K = kLds ? s_maj[(bk * P.my + bj) * P.mx + bi] : P.majorant[maj_base + (bk * P.my + bj) * P.mx + bi];
+            if (__float_as_uint(kmaj) == kNoMajorant)
+                kmaj = kLds ? s_maj[(bk * P.my + bj) * P.mx + bi] : P.majorant[maj_base + (bk * P.my + bj) * P.mx + bi];
+            K = kmaj;
             const float Km = fabsf(K);
             const float x0 = (float)bi * P.cx, y0 = (float)bj * P.cy, z0 = (float)bk * P.cz;
             float tx = INFINITY, ty = INFINITY, tz = INFINITY;
@@ -617,6 +625,7 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
                     py = (float)(bj + 1) * P.cy;
                 }
             }
+            kmaj = __uint_as_float(kNoMajorant);  // crossed into another cell
         }
         if (outcome == kWalking) continue;  // same free path next iteration
         tau = -1.f;

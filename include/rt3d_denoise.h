@@ -77,6 +77,16 @@ rt3d_status rt3d_dn_conv3d_fwd_head(const rt3d_dn_conv* c, const uint16_t* x1, c
                                     const float* bias, int32_t relu, const uint16_t* hw, const float* hb, int32_t hcols,
                                     float* hy, void* stream);
 
+/* The first layer followed by the 2x2x2 average pooling of its output, in
+ * one launch (inference): c describes the packed first layer (c1 = 4, c2 =
+ * 0, ksize 3, cout 32, up1 0, yf_cols 0) on even D, H, W.  y receives the
+ * BF16 layer output [D][H][W][32] and ypool its pooling [D/2][H/2][W/2][32],
+ * both bitwise equal to rt3d_dn_conv3d_fwd (y1 = y, o1 = 32) followed by
+ * rt3d_dn_pool2; the full-resolution output is not read back.  Device
+ * pointers; RT3D_EINVAL for any other shape. */
+rt3d_status rt3d_dn_conv3d_fwd_pool(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* w, const float* bias,
+                                    int32_t relu, uint16_t* y, uint16_t* ypool, void* stream);
+
 /* wt[ci][k^3 - 1 - t][co] = w[co][t][ci]: the kernel of the data gradient. */
 rt3d_status rt3d_dn_flip_weights(const uint16_t* w, uint16_t* wt, int32_t cout, int32_t cin, int32_t ksize,
                                  void* stream);
@@ -141,10 +151,25 @@ rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* strea
 /* Network input per voxel: channel 0 = hdir/scale, 1 = hdif/scale,
  * 2 = ln(1 + 20 k_ext dz), 3 = ln(1 + 200 k_abs dz), channels 4..cpad-1 = 0
  * (feat BF16 [vox][cpad], cpad 4 or a multiple of 16); base FP32 [vox][2] = (hdir/scale, hdif/scale), the
- * residual the network corrects.  hdir, hdif: FP32 heating fields; k_ext,
+ * residual the network corrects (NULL: not written).  hdir, hdif: FP32 heating fields; k_ext,
  * k_abs: FP32 [vox] extinction and absorption coefficients (m^-1). */
 rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
                              float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream);
+
+/* Field scale of the network input: work[0] = (mean hdir + mean hdif) / 2
+ * (1 if that is not positive), summed in FP64 in a fixed order (bitwise
+ * reproducible).  hdir, hdif: FP32 device [nvox]; work: FP64 device
+ * [RT3D_DN_SCALE_WORK] (work[1..] are partial sums). */
+#define RT3D_DN_SCALE_WORK 2049
+rt3d_status rt3d_dn_field_scale(const float* hdir, const float* hdif, uint64_t nvox, double* work, void* stream);
+
+/* Inference output in one pass: hdir[v] = max(out[v][0] + base0, 0) scale,
+ * hdif[v] = max(out[v][1] + base1, 0) scale with (base0, base1) the residual
+ * base rt3d_dn_features forms from hdir_in, hdif_in and scale; bitwise
+ * rt3d_dn_features' base, rt3d_dn_mse (pred) and rt3d_dn_unfeature in turn.
+ * out: FP32 [nvox][cpad] network output; all FP32 device arrays. */
+rt3d_status rt3d_dn_residual_unfeature(const float* out, int32_t cpad, const float* hdir_in, const float* hdif_in,
+                                       float scale, uint64_t nvox, float* hdir, float* hdif, void* stream);
 
 /* hdir[v] = max(pred[v][0], 0) scale, hdif[v] = max(pred[v][1], 0) scale. */
 rt3d_status rt3d_dn_unfeature(const float* pred, float scale, uint64_t nvox, float* hdir, float* hdif,

@@ -262,6 +262,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
             bv[1] = bn[1];
         }
     }
+    if (!a.yf && a.y1 && a.o1 == a.cout && nct == 2) {
+        // BF16 output through LDS, as in conv3_c4_kernel: each wave writes
+        // one output row of its slab (32 voxels x 64 channels, 4 KiB) to its
+        // own slice of the halo tile and stores it as 16-byte pieces (8
+        // channels of one voxel), 4 per lane, instead of 2-byte stores
+        static_assert(4 * 32 * 64 * 2 <= tile_slots(kHaloVox) * 16, "row scratch exceeds the halo tile");
+        __syncthreads();  // every wave is done reading the halo
+        uint16_t* row = reinterpret_cast<uint16_t*>(tile) + wave * (32 * 64);
+        float bias[2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) bias[ct] = a.bias ? a.bias[co0 + 32 * ct + m] : 0.0f;
+#pragma unroll
+        for (int oz = 0; oz < kZ; ++oz) {
+            const int zz = z0 + oz;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int y = y0 + row0 + r;
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        float v = acc[oz][r][ct][e] + bias[ct];
+                        if (a.relu) v = fmaxf(v, 0.0f);
+                        row[(8 * (e >> 2) + 4 * half + (e & 3)) * 64 + 32 * ct + m] = f2bf(v);
+                    }
+                // LDS instructions of one wave complete in order; the barrier
+                // keeps the compiler from moving the reads across the writes
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int it = 0; it < 4; ++it) {
+                    const int q = it * 64 + lane;  // voxel q / 8, channels co0 + 8 (q % 8) ..
+                    const int x = x0 + (q >> 3);
+                    const uint4 v = *reinterpret_cast<const uint4*>(row + (q >> 3) * 64 + 8 * (q & 7));
+                    if (zz < a.D && y < a.H && x < a.W)
+                        *reinterpret_cast<uint4*>(a.y1 + (((long)zz * a.H + y) * a.W + x) * a.cout + co0 + 8 * (q & 7)) = v;
+                }
+                __builtin_amdgcn_wave_barrier();  // the next row's writes follow these reads
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int oz = 0; oz < kZ; ++oz) {
         const int zz = z0 + oz;
@@ -310,7 +351,10 @@ constexpr int kHaloY32 = kTY32 + 2;
 constexpr int kZ32 = 2;
 constexpr int kHaloVox32 = (kZ32 + 2) * kHaloY32 * kHaloX;
 // the fused head reuses the halo tile: 4 waves x kZ32 x 4 rows x 32 x 32 BF16
+// activations, then per wave one output row of 32 voxels x 2 FP32
 static_assert(4 * kZ32 * 4 * 32 * 32 * 2 <= kHaloVox32 * 2 * 16, "head scratch exceeds the halo tile");
+constexpr int kHeadOutOffset = 4 * kZ32 * 4 * 32 * 32 * 2;  // bytes
+static_assert(kHeadOutOffset + 4 * 32 * 2 * 4 <= kHaloVox32 * 2 * 16, "head output scratch exceeds the halo tile");
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) conv3_c32_kernel(const ConvArgs a) {
     __shared__ uint4 tile[tile_slots(kHaloVox32)];
@@ -407,6 +451,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
                 for (int c = 0; c < 2; ++c) {
                     const uint4 av = *(const uint4*)(ht + ((oz * 4 + o) * 32 + m) * 32 + 16 * c + 8 * half);
                     h = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(hwv[c]), h, 0, 0, 0);
+                }
+                if (a.hcols == 2) {
+                    // the two used outputs of the row go through LDS (behind
+                    // the activations' part of the tile), so that the row is
+                    // stored as one 8-byte piece per voxel by 32 lanes instead
+                    // of 16 stores of 4 bytes by 4 lanes each
+                    float* hrow = reinterpret_cast<float*>(tile) + kHeadOutOffset / 4 + wave * 64;
+                    if (n < 2) {
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) hrow[(8 * (e >> 2) + 4 * half + (e & 3)) * 2 + n] = h[e] + hbias;
+                    }
+                    // LDS instructions of one wave complete in order; the
+                    // barrier keeps the compiler from moving the read across
+                    // the writes
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < 32) {
+                        const float2 v = *reinterpret_cast<const float2*>(hrow + 2 * lane);
+                        if (x0 + lane < a.W)
+                            *reinterpret_cast<float2*>(a.hy + (((long)zz * a.H + y) * a.W + x0 + lane) * 2) = v;
+                    }
+                    __builtin_amdgcn_wave_barrier();  // the next row's writes follow this read
+                    continue;
                 }
                 if (n >= a.hcols) continue;
 #pragma unroll
@@ -527,6 +593,40 @@ __global__ void __launch_bounds__(256) conv3_c4_kernel(const ConvArgs a) {
         }
     const int n = m;
     const float bias = a.bias ? a.bias[n] : 0.0f;
+    if (!a.yf && a.y1 && a.o1 == 32) {
+        // BF16 output through LDS: a lane holds one channel of 16 voxels, so
+        // direct stores would be 2 bytes each; each wave instead writes one
+        // output row (32 voxels x 32 channels, 2 KiB) to its own slice of the
+        // halo tile (every wave is done reading it) and stores it back as
+        // 16-byte pieces (8 channels of one voxel), 2 per lane
+        static_assert(4 * 32 * 32 * 2 <= kHaloVoxC4 * 8, "row scratch exceeds the halo tile");
+        __syncthreads();
+        uint16_t* row = reinterpret_cast<uint16_t*>(tile) + wave * (32 * 32);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int y = y0 + row0 + o;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                float v = acc[o][e] + bias;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                row[(8 * (e >> 2) + 4 * half + (e & 3)) * 32 + n] = f2bf(v);
+            }
+            // LDS instructions of one wave complete in order: the reads below
+            // see this row; the barrier only keeps the compiler from moving
+            // them across the writes
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                const int q = it * 64 + lane;  // 16-byte piece: voxel q / 4, channels 8 (q % 4) ..
+                const int x = x0 + (q >> 2);
+                const uint4 v = *reinterpret_cast<const uint4*>(row + (q >> 2) * 32 + 8 * (q & 3));
+                if (y < a.H && x < a.W)
+                    *reinterpret_cast<uint4*>(a.y1 + (((long)zz * a.H + y) * a.W + x) * 32 + 8 * (q & 3)) = v;
+            }
+            __builtin_amdgcn_wave_barrier();  // the next row's writes follow these reads
+        }
+        return;
+    }
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         const int y = y0 + row0 + o;
@@ -541,6 +641,148 @@ __global__ void __launch_bounds__(256) conv3_c4_kernel(const ConvArgs a) {
             if (a.yf && n < a.yf_cols) a.yf[vox * a.yf_cols + n] = v;
             if (a.y1) a.y1[vox * a.o1 + n] = f2bf(v);
         }
+    }
+}
+
+// The first layer and the 2x2x2 average pooling of its output in one launch
+// (inference).  A workgroup computes both output planes of one pooled plane
+// from four staged input planes (the MFMAs of each output in
+// conv3_c4_kernel's order), stores them as conv3_c4_kernel does, and pools
+// each wave's pairs of output rows from LDS as they pass, adding in
+// pool2_kernel's order (z, then y, then x, in FP32) with the sums of the
+// first plane kept in registers: the full-resolution and the pooled output
+// are bitwise those of the two separate launches, and the full-resolution
+// output is not read back.  D, H, W even.
+constexpr int kHaloVoxC4P = 4 * kHaloY32 * kHaloX;
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+conv3_c4_pool_kernel(const ConvArgs a, uint16_t* __restrict__ yp) {
+    __shared__ uint2 tile[kHaloVoxC4P];
+    __shared__ uint4 rows[4 * 2 * 32 * 32 * 2 / 16];  // per wave two output rows, 32 voxels x 32 BF16 channels
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, half = lane >> 5;
+    const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY32 - 1) / kTY32;
+    long b = blockIdx.x;
+    const int txi = (int)(b % tiles_x);
+    b /= tiles_x;
+    const int tyi = (int)(b % tiles_y);
+    const int zp = (int)(b / tiles_y);  // pooled plane: output planes 2 zp, 2 zp + 1
+    const int z0 = 2 * zp;
+    const int x0 = txi * kTX, y0 = tyi * kTY32;
+    const int row0 = 4 * wave;
+    {
+        constexpr int kPer = (kHaloVoxC4P + 255) / 256, SB = 4;
+#pragma unroll 1
+        for (int j0 = 0; j0 < kPer; j0 += SB) {
+            uint2 vv[SB];
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int v = threadIdx.x + 256 * (j0 + j);
+                const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+                const bool in = x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D;
+                const int xc = min(max(x, 0), a.W - 1), yc = min(max(y, 0), a.H - 1), zc = min(max(z, 0), a.D - 1);
+                vv[j] = *(in ? (const uint2*)(a.x1 + (((long)zc * a.H + yc) * a.W + xc) * 4)
+                             : reinterpret_cast<const uint2*>(dn_zero16));
+            }
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int v = threadIdx.x + 256 * (j0 + j);
+                if (j0 + j < kPer && v < kHaloVoxC4P) tile[v] = vv[j];
+            }
+        }
+    }
+    uint4 bv[9];
+    const uint16_t* wrow = a.w + (long)m * 27 * 4;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const uint2 lo = *(const uint2*)(wrow + (q * 3 + 2 * half) * 4);
+        const uint2 hi = half ? make_uint2(0u, 0u) : *(const uint2*)(wrow + (q * 3 + 1) * 4);
+        bv[q] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    }
+    __syncthreads();
+    const float bias = a.bias ? a.bias[m] : 0.0f;
+    uint16_t* scr = reinterpret_cast<uint16_t*>(rows) + wave * (2 * 32 * 32);
+    const int pv = lane >> 2, cg = lane & 3;  // this lane's pooled voxel of a pooled row and 8-channel group
+    float s[2][8];
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[pr][k] = 0.0f;
+#pragma unroll 1
+    for (int oz = 0; oz < 2; ++oz) {
+        f32x16 acc[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[o][e] = 0.0f;
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const int i = ((oz + dz) * kHaloY32 + row0 + r) * kHaloX + m;  // voxel x-1 of output column m
+                const uint2 lo = tile[i + 2 * half];
+                const uint2 hi = half ? make_uint2(0u, 0u) : tile[i + 1];
+                const uint4 av = make_uint4(lo.x, lo.y, hi.x, hi.y);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const int dy = r - o;
+                    if (dy >= 0 && dy <= 2)
+                        acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[dz * 3 + dy]),
+                                                                         acc[o], 0, 0, 0);
+                }
+            }
+        const int zz = z0 + oz;
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+#pragma unroll
+            for (int oo = 0; oo < 2; ++oo)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float v = acc[2 * pr + oo][e] + bias;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    scr[(oo * 32 + 8 * (e >> 2) + 4 * half + (e & 3)) * 32 + m] = f2bf(v);
+                }
+            // LDS instructions of one wave complete in order; the barrier
+            // keeps the compiler from moving the reads across the writes
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int oo = 0; oo < 2; ++oo) {
+                const int y = y0 + row0 + 2 * pr + oo;
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    const int q = it * 64 + lane;  // voxel q / 4, channels 8 (q % 4) ..
+                    const int x = x0 + (q >> 2);
+                    const uint4 v = *reinterpret_cast<const uint4*>(scr + (oo * 32 + (q >> 2)) * 32 + 8 * (q & 3));
+                    if (y < a.H && x < a.W)
+                        *reinterpret_cast<uint4*>(a.y1 + (((long)zz * a.H + y) * a.W + x) * 32 + 8 * (q & 3)) = v;
+                }
+            }
+#pragma unroll
+            for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+                for (int xx = 0; xx < 2; ++xx) {
+                    const uint4 u = *reinterpret_cast<const uint4*>(scr + (yy * 32 + 2 * pv + xx) * 32 + 8 * cg);
+                    const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        s[pr][2 * k] += bf2f((uint16_t)(wd[k] & 0xffffu));
+                        s[pr][2 * k + 1] += bf2f((uint16_t)(wd[k] >> 16));
+                    }
+                }
+            __builtin_amdgcn_wave_barrier();  // the next rows' writes follow these reads
+        }
+    }
+    const int hh = a.H / 2, wh = a.W / 2;
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+        const int yh = (y0 + row0) / 2 + pr, xh = x0 / 2 + pv;
+        if (yh >= hh || xh >= wh) continue;
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = (uint32_t)f2bf(0.125f * s[pr][2 * k]) | ((uint32_t)f2bf(0.125f * s[pr][2 * k + 1]) << 16);
+        *reinterpret_cast<uint4*>(yp + (((long)zp * hh + yh) * wh + xh) * 32 + 8 * cg) = make_uint4(o[0], o[1], o[2], o[3]);
     }
 }
 
@@ -823,8 +1065,87 @@ __global__ void features_kernel(const float* __restrict__ hdir, const float* __r
         f[2] = f2bf(__logf(1.0f + 20.0f * k_ext[v] * dz));
         f[3] = f2bf(__logf(1.0f + 200.0f * k_abs[v] * dz));
         for (int q = 4; q < cpad; ++q) f[q] = 0;
-        base[2 * v] = a;
-        base[2 * v + 1] = b;
+        if (base) {
+            base[2 * v] = a;
+            base[2 * v + 1] = b;
+        }
+    }
+}
+
+// Sums of two FP32 fields in FP64, in a fixed order: per-block partial sums
+// over a fixed grid of kSumBlocks blocks, then one block over the partials.
+constexpr int kSumBlocks = 1024;
+
+__global__ void field_sum_kernel(const float* __restrict__ a, const float* __restrict__ b, size_t n,
+                                 double* __restrict__ partial) {
+    __shared__ double sa[256], sb[256];
+    double xa = 0.0, xb = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        xa += (double)a[i];
+        xb += (double)b[i];
+    }
+    sa[threadIdx.x] = xa;
+    sb[threadIdx.x] = xb;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sa[0];
+        partial[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
+// scale = (mean a + mean b) / 2, or 1 if that is not positive
+__global__ void field_scale_kernel(const double* __restrict__ partial, size_t n, double* __restrict__ scale) {
+    __shared__ double sa[256], sb[256];
+    double xa = 0.0, xb = 0.0;
+    for (int k = threadIdx.x; k < kSumBlocks; k += 256) {
+        xa += partial[2 * k];
+        xb += partial[2 * k + 1];
+    }
+    sa[threadIdx.x] = xa;
+    sb[threadIdx.x] = xb;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = (sa[0] / (double)n + sb[0] / (double)n) / 2.0;
+        scale[0] = m > 0.0 ? m : 1.0;
+    }
+}
+
+// a * b rounded to FP32 on its own: the library is built with FP contraction,
+// which would otherwise fuse it with a following addition into one FMA (and
+// the backend does so even where the source forbids it)
+__device__ __forceinline__ float mul_rounded(float a, float b) {
+    float r;
+    asm("v_mul_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Inference: the residual head and the split back into heating fields in one
+// pass, hdir[v] = max(out[v][0] + hdir_in[v] / scale, 0) scale (and hdif
+// alike), with the division as features_kernel forms it (times the FP32
+// reciprocal, rounded before the addition), so the result is bitwise that of
+// features_kernel's base, mse_kernel and unfeature_kernel in turn.
+__global__ void residual_unfeature_kernel(const float* __restrict__ out, int cpad, const float* __restrict__ hdir_in,
+                                          const float* __restrict__ hdif_in, float inv_scale, float scale, size_t nvox,
+                                          float* __restrict__ hdir, float* __restrict__ hdif) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
+        const float p0 = out[v * cpad] + mul_rounded(hdir_in[v], inv_scale);
+        const float p1 = out[v * cpad + 1] + mul_rounded(hdif_in[v], inv_scale);
+        hdir[v] = fmaxf(p0, 0.0f) * scale;
+        hdif[v] = fmaxf(p1, 0.0f) * scale;
     }
 }
 
@@ -845,6 +1166,22 @@ __global__ void unfeature_kernel(const float* __restrict__ pred, float scale, si
 extern "C" {
 
 const char* rt3d_dn_last_error(void) { return d_err; }
+
+rt3d_status rt3d_dn_conv3d_fwd_pool(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* w, const float* bias,
+                                    int32_t relu, uint16_t* y, uint16_t* ypool, void* stream) {
+    if (!c || !x1 || !w || !y || !ypool) return RT3D_EINVAL;
+    if (c->c1 != 4 || c->c2 != 0 || c->ksize != 3 || c->cout != 32 || c->up1 || c->yf_cols) return RT3D_EINVAL;
+    if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->D % 2 || c->H % 2 || c->W % 2) return RT3D_EINVAL;
+    ConvArgs a;
+    memset(&a, 0, sizeof a);
+    a.x1 = x1; a.c1 = 4; a.w = w; a.bias = bias; a.y1 = y; a.o1 = 32;
+    a.D = c->D; a.H = c->H; a.W = c->W; a.cout = 32; a.relu = relu ? 1 : 0;
+    const long tiles = (long)(c->D / 2) * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
+    if (tiles > 0x7fffffffL) return RT3D_EINVAL;
+    hipLaunchKernelGGL(conv3_c4_pool_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a, ypool);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
 
 rt3d_status rt3d_dn_conv3d_fwd(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* x2, const uint16_t* w,
                                const float* bias, int32_t relu, uint16_t* y1, uint16_t* y2, int32_t o1, float* yf,
@@ -1086,7 +1423,7 @@ rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* strea
 
 rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
                              float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream) {
-    if (!hdir || !hdif || !k_ext || !k_abs || !feat || !base || (cpad != 4 && (cpad < 16 || cpad % 16)) ||
+    if (!hdir || !hdif || !k_ext || !k_abs || !feat || (cpad != 4 && (cpad < 16 || cpad % 16)) ||
         !(scale > 0.0f))
         return RT3D_EINVAL;
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, hdir, hdif, k_ext,
@@ -1100,6 +1437,25 @@ rt3d_status rt3d_dn_unfeature(const float* pred, float scale, uint64_t nvox, flo
     if (!pred || !hdir || !hdif) return RT3D_EINVAL;
     hipLaunchKernelGGL(unfeature_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, pred, scale,
                        (size_t)nvox, hdir, hdif);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_field_scale(const float* hdir, const float* hdif, uint64_t nvox, double* work, void* stream) {
+    if (!hdir || !hdif || !work || nvox == 0) return RT3D_EINVAL;
+    hipLaunchKernelGGL(field_sum_kernel, dim3(kSumBlocks), dim3(256), 0, (hipStream_t)stream, hdir, hdif,
+                       (size_t)nvox, work + 1);
+    DN_TRY(hipGetLastError());
+    hipLaunchKernelGGL(field_scale_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, work + 1, (size_t)nvox, work);
+    DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_residual_unfeature(const float* out, int32_t cpad, const float* hdir_in, const float* hdif_in,
+                                       float scale, uint64_t nvox, float* hdir, float* hdif, void* stream) {
+    if (!out || !hdir_in || !hdif_in || !hdir || !hdif || cpad < 2 || !(scale > 0.0f)) return RT3D_EINVAL;
+    hipLaunchKernelGGL(residual_unfeature_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, out,
+                       cpad, hdir_in, hdif_in, 1.0f / scale, scale, (size_t)nvox, hdir, hdif);
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }

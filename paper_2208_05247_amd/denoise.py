@@ -55,6 +55,7 @@ def load():
     sig = {
         "rt3d_dn_conv3d_fwd": [ctypes.POINTER(_Conv), P, P, P, P, I, P, P, I, P, P],
         "rt3d_dn_conv3d_fwd_head": [ctypes.POINTER(_Conv), P, P, P, P, I, P, P, I, P, P],
+        "rt3d_dn_conv3d_fwd_pool": [ctypes.POINTER(_Conv), P, P, P, I, P, P, P],
         "rt3d_dn_flip_weights": [P, P, I, I, I, P],
         "rt3d_dn_conv3d_wgrad": [ctypes.POINTER(_Conv), P, P, P, P, P, P],
         "rt3d_dn_conv3d_wgrad_ws": [ctypes.POINTER(_Conv), P, P, P, P, P, P, ctypes.c_size_t, P],
@@ -67,6 +68,8 @@ def load():
         "rt3d_dn_to_bf16": [P, P, U, P],
         "rt3d_dn_features": [P, P, P, P, ctypes.c_float, ctypes.c_float, U, I, P, P, P],
         "rt3d_dn_unfeature": [P, ctypes.c_float, U, P, P, P],
+        "rt3d_dn_field_scale": [P, P, U, P, P],
+        "rt3d_dn_residual_unfeature": [P, I, P, P, ctypes.c_float, U, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -141,6 +144,18 @@ def conv_fwd_head(x1, x2, w, bias, relu, hw, hb, out, up1=False):
     c = _Conv(D, H, W, c1, c2, 32, 3, 1 if up1 else 0, 0)
     _check(load().rt3d_dn_conv3d_fwd_head(ctypes.byref(c), _p(x1), _p(x2), _p(w), _p(bias), int(relu), _p(hw),
                                           _p(hb), int(out.shape[-1]), _p(out), _s()), "rt3d_dn_conv3d_fwd_head")
+
+
+def conv_fwd_pool(x1, w, bias, relu, y, ypool):
+    """The packed first layer (x1 BF16 [D][H][W][4], w [32][27][4]) and the
+    2x2x2 average pooling of its output in one launch: y [D][H][W][32] and
+    ypool [D/2][H/2][W/2][32], bitwise conv_fwd followed by pool2."""
+    D, H, W, c1 = x1.shape
+    if c1 != 4 or tuple(y.shape) != (D, H, W, 32) or tuple(ypool.shape) != (D // 2, H // 2, W // 2, 32):
+        raise ValueError("conv_fwd_pool: x1 [D][H][W][4], y [D][H][W][32], ypool [D/2][H/2][W/2][32]")
+    c = _Conv(D, H, W, 4, 0, 32, 3, 0, 0)
+    _check(load().rt3d_dn_conv3d_fwd_pool(ctypes.byref(c), _p(x1), _p(w), _p(bias), int(relu), _p(y), _p(ypool),
+                                          _s()), "rt3d_dn_conv3d_fwd_pool")
 
 
 def flip(w, cout, cin, ksize, out):
@@ -286,13 +301,14 @@ class Denoiser:
             raise ValueError("training needs the 16-channel features")
         a = {"x0": feat}
         if cf == 4:
+            # the packed first layer and its pooling in one launch
             L = self.layers[0]
             a["e0"] = bf16_empty(D, H, W, L.cout)
-            conv_fwd(feat, None, self.pb["e0"][:, :, :4].contiguous(), self.bias["e0"], L.relu, L.cout, L.ksize,
-                     y1=a["e0"])
+            a["p0"] = bf16_empty(D // 2, H // 2, W // 2, L.cout)
+            conv_fwd_pool(feat, self.pb["e0"][:, :, :4].contiguous(), self.bias["e0"], L.relu, a["e0"], a["p0"])
         else:
             a["e0"] = self._conv("e0", feat)
-        a["p0"] = pool2(a["e0"])
+            a["p0"] = pool2(a["e0"])
         a["e1"] = self._conv("e1", a["p0"])
         a["p1"] = pool2(a["e1"])
         a["e2"] = self._conv("e2", a["p1"])
@@ -416,9 +432,18 @@ def features(hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, k_abs:
     return feat, base
 
 
+SCALE_WORK = 2049  # RT3D_DN_SCALE_WORK
+
+
 def field_scale(hdir: torch.Tensor, hdif: torch.Tensor) -> float:
-    s = float((hdir.double().mean() + hdif.double().mean()).item()) / 2.0
-    return s if s > 0 else 1.0
+    """(mean hdir + mean hdif) / 2 (1 if not positive), reduced on the device
+    in FP64 in a fixed order (rt3d_dn_field_scale); returned to the host."""
+    if hdir.dtype != torch.float32 or hdif.dtype != torch.float32 or hdir.shape != hdif.shape:
+        raise ValueError("field_scale: two FP32 fields of one shape")
+    work = torch.empty(SCALE_WORK, dtype=torch.float64, device=hdir.device)
+    _check(load().rt3d_dn_field_scale(_p(hdir.contiguous()), _p(hdif.contiguous()), hdir.numel(), _p(work), _s()),
+           "rt3d_dn_field_scale")
+    return float(work[0].item())
 
 
 def mse(out: torch.Tensor, base: torch.Tensor, target: Optional[torch.Tensor], want_grad: bool):
@@ -444,9 +469,13 @@ def denoise(net: Denoiser, hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.
             dz: float):
     """Inference: denoised (hdir, hdif), same units as the inputs."""
     s = field_scale(hdir, hdif)
-    feat, base = features(hdir, hdif, k_ext, k_abs, dz, s, cpad=4)
+    D, H, W = hdir.shape
+    feat = bf16_empty(D, H, W, 4)
+    # the residual base is not stored: the output pass forms it again
+    _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), _p(k_abs), float(dz), float(s), hdir.numel(), 4,
+                                   _p(feat), None, _s()), "rt3d_dn_features")
     out = net.forward(feat)
-    pred, _, _ = mse(out, base, None, want_grad=False)
     od, of = torch.empty_like(hdir), torch.empty_like(hdif)
-    _check(load().rt3d_dn_unfeature(_p(pred), float(s), hdir.numel(), _p(od), _p(of), _s()), "rt3d_dn_unfeature")
+    _check(load().rt3d_dn_residual_unfeature(_p(out), out.shape[-1], _p(hdir), _p(hdif), float(s), hdir.numel(),
+                                             _p(od), _p(of), _s()), "rt3d_dn_residual_unfeature")
     return od, of

@@ -283,6 +283,58 @@ def test_training_is_bitwise_reproducible(dn):
         assert torch.equal(nets[0].bias[k], nets[1].bias[k]), k
 
 
+def test_field_scale_and_fused_output(dn):
+    """rt3d_dn_field_scale against the FP64 means (and reproducible to the
+    bit); rt3d_dn_residual_unfeature bitwise equal to features' base, the
+    residual head (rt3d_dn_mse) and rt3d_dn_unfeature in turn."""
+    g = torch.Generator().manual_seed(23)
+    for shape in ((3, 5, 7), (16, 64, 96)):
+        hd = (torch.rand(shape, generator=g) * 3.0).cuda()
+        hf = (torch.rand(shape, generator=g) * 0.5).cuda()
+        s = dn.field_scale(hd, hf)
+        ref = (hd.double().mean().item() + hf.double().mean().item()) / 2.0
+        assert abs(s - ref) <= 1e-12 * ref
+        assert dn.field_scale(hd, hf) == s
+        assert dn.field_scale(torch.zeros_like(hd), torch.zeros_like(hf)) == 1.0
+        ke = torch.rand(shape, generator=g).cuda() * 0.01
+        out = torch.randn(*shape, 4, generator=g).cuda()
+        feat, base = dn.features(hd, hf, ke, 0.1 * ke, 20.0, s, cpad=4)
+        pred, _, _ = dn.mse(out, base, None, want_grad=False)
+        od_ref, of_ref = torch.empty_like(hd), torch.empty_like(hf)
+        dn._check(dn.load().rt3d_dn_unfeature(dn._p(pred), float(s), hd.numel(), dn._p(od_ref), dn._p(of_ref),
+                                              dn._s()), "unfeature")
+        od, of = torch.empty_like(hd), torch.empty_like(hf)
+        dn._check(dn.load().rt3d_dn_residual_unfeature(dn._p(out), 4, dn._p(hd), dn._p(hf), float(s), hd.numel(),
+                                                       dn._p(od), dn._p(of), dn._s()), "residual_unfeature")
+        assert torch.equal(od.view(torch.int32), od_ref.view(torch.int32))
+        assert torch.equal(of.view(torch.int32), of_ref.view(torch.int32))
+        assert (od_ref == 0).any() and (od_ref > 0).any()  # both sides of the clamp
+
+
+def test_first_layer_with_pooling_is_bitwise(dn):
+    """rt3d_dn_conv3d_fwd_pool: the packed first layer and its 2x2x2 pooling
+    in one launch equal the two separate launches bit for bit, partial tiles
+    in y and x included; shapes it does not take are refused."""
+    g = torch.Generator().manual_seed(17)
+    for D, H, W in ((4, 20, 36), (2, 16, 32), (6, 34, 66)):
+        x = torch.randn(D, H, W, 4, generator=g).to(torch.bfloat16).cuda()
+        w = (torch.randn(32, 27, 4, generator=g) * 0.2).to(torch.bfloat16).cuda()
+        b = (torch.randn(32, generator=g) * 0.1).cuda()
+        for relu in (True, False):
+            y_ref = torch.empty(D, H, W, 32, dtype=torch.bfloat16, device="cuda")
+            dn.conv_fwd(x, None, w, b, relu, 32, 3, y1=y_ref)
+            p_ref = dn.pool2(y_ref)
+            y = torch.full((D, H, W, 32), 7.0, dtype=torch.bfloat16, device="cuda")
+            p = torch.full((D // 2, H // 2, W // 2, 32), 7.0, dtype=torch.bfloat16, device="cuda")
+            dn.conv_fwd_pool(x, w, b, relu, y, p)
+            assert torch.equal(y.view(torch.int16), y_ref.view(torch.int16)), (D, H, W, relu)
+            assert torch.equal(p.view(torch.int16), p_ref.view(torch.int16)), (D, H, W, relu)
+    x = torch.zeros(3, 16, 32, 4, dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(Exception):
+        dn.conv_fwd_pool(x, w, b, True, torch.empty(3, 16, 32, 32, dtype=torch.bfloat16, device="cuda"),
+                         torch.empty(1, 8, 16, 32, dtype=torch.bfloat16, device="cuda"))
+
+
 def test_packed_first_layer(dn):
     """The first layer with 4 input channels (three x-taps per MFMA K-chunk)
     against the FP64 convolution, partial tiles included, and the inference

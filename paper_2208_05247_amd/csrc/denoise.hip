@@ -388,26 +388,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) c
 #pragma unroll
             for (int t = 0; t < 9; ++t)
                 bv[t] = *(const uint4*)(a.w + ((long)m * 27 + dz * 9 + t) * cin + c0 + 8 * half);
+            // the 12 staged rows (2 output planes x 6 input rows) this wave
+            // reads for this kernel slice, each as 3 x-shifted fragments; the
+            // fragments of the next row are read before this row's MFMAs
+            // run, so the LDS latency hides behind them
+            auto row_frags = [&](int step, uint4* av) {
+                const int oz = step / 6, r = step % 6;  // output plane oz reads staged plane oz + dz
 #pragma unroll
-            for (int oz = 0; oz < kZ32; ++oz)
+                for (int dx = 0; dx < 3; ++dx)
+                    av[dx] = tile[(((oz + dz) * kHaloY32 + row0 + r) * kHaloX + m + dx) * 2 + half];
+            };
+            uint4 cur[3], nxt[3];
+            row_frags(0, cur);
 #pragma unroll
-                for (int r = 0; r < 6; ++r) {
-                    // keeps the scheduler from hoisting every LDS read of the
-                    // slice ahead of the MFMAs (it would spill at 2 waves/SIMD)
-                    __builtin_amdgcn_sched_barrier(0);
+            for (int step = 0; step < kZ32 * 6; ++step) {
+                const int oz = step / 6, r = step % 6;
+                if (step + 1 < kZ32 * 6) row_frags(step + 1, nxt);
+                // keeps the scheduler from hoisting the reads of later rows
+                // ahead of these MFMAs (it would spill at 2 waves/SIMD)
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) {
-                        // output plane oz reads staged plane oz + dz
-                        const uint4 av = tile[(((oz + dz) * kHaloY32 + row0 + r) * kHaloX + m + dx) * 2 + half];
+                for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-                        for (int o = 0; o < 4; ++o) {
-                            const int dy = r - o;  // output row o reads halo row o + dy
-                            if (dy >= 0 && dy <= 2)
-                                acc[oz][o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                    as_bf16x8(av), as_bf16x8(bv[dy * 3 + dx]), acc[oz][o], 0, 0, 0);
-                        }
+                    for (int o = 0; o < 4; ++o) {
+                        const int dy = r - o;  // output row o reads halo row o + dy
+                        if (dy >= 0 && dy <= 2)
+                            acc[oz][o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                as_bf16x8(cur[dx]), as_bf16x8(bv[dy * 3 + dx]), acc[oz][o], 0, 0, 0);
                     }
-                }
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) cur[dx] = nxt[dx];
+            }
         }
     }
     const int n = m;

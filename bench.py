@@ -284,7 +284,7 @@ def denoiser_flops(net, D, H, W) -> float:
     flops = 0.0
     for L in net.layers:
         level = {"e0": 0, "e1": 1, "e2": 2, "b": 3, "d2": 2, "d1": 1, "d0": 0, "head": 0}[L.name]
-        cin = 4 if L.name == "e0" else L.c1 + L.c2
+        cin = net.n_in if L.name == "e0" else L.c1 + L.c2
         cout = dn.NOUT if L.name == "head" else L.cout
         flops += 2.0 * L.ksize ** 3 * cin * cout * (D * H * W) / 8 ** level
     return flops
@@ -298,25 +298,32 @@ def denoiser_measurement(reps: int = 3) -> dict:
     inference (features, every convolution, pooling, residual head)."""
     import torch
     from paper_2208_05247_amd import denoise as dn
+    from paper_2208_05247_amd import experiment as ex
+    from paper_2208_05247_amd.synthetic import Grid
 
     D, H, W = 128, 1024, 1024
-    net = dn.Denoiser(base=32, seed=0)
+    n_in = ex.committed_denoiser_inputs()
+    net = dn.Denoiser(base=32, seed=0, n_in=n_in)
     g = torch.Generator(device="cuda").manual_seed(1)
     hd = torch.rand(D, H, W, device="cuda", generator=g)
     hf = torch.rand(D, H, W, device="cuda", generator=g)
     ke = torch.rand(D, H, W, device="cuda", generator=g) * 0.01
+    ka = 0.1 * ke
+    grid = Grid(W, H, D, 25.0, 25.0, 20.0)
+    direct = {"grid": grid, "sza": 60.0, "azimuth": 0.0, "direct_fraction": 0.88,
+              "layer_scale": ex.layer_scale(grid)} if n_in == 5 else None
     flops = denoiser_flops(net, D, H, W)
-    dn.denoise(net, hd, hf, ke, 0.1 * ke, 20.0)
+    dn.denoise(net, hd, hf, ke, ka, 20.0, direct=direct)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dn.denoise(net, hd, hf, ke, 0.1 * ke, 20.0)
+        dn.denoise(net, hd, hf, ke, ka, 20.0, direct=direct)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     achieved = flops / (ms * 1e-3) / 1e12
-    return {"grid": [D, H, W], "parameters": net.n_params(), "ms_per_inference": ms,
+    return {"grid": [D, H, W], "inputs": n_in, "parameters": net.n_params(), "ms_per_inference": ms,
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "flops_per_call": flops}}
 

@@ -82,8 +82,13 @@ rt3d_status rt3d_dn_conv3d_fwd_head(const rt3d_dn_conv* c, const uint16_t* x1, c
  * 0, ksize 3, cout 32, up1 0, yf_cols 0) on even D, H, W.  y receives the
  * BF16 layer output [D][H][W][32] and ypool its pooling [D/2][H/2][W/2][32],
  * both bitwise equal to rt3d_dn_conv3d_fwd (y1 = y, o1 = 32) followed by
- * rt3d_dn_pool2; the full-resolution output is not read back.  Device
- * pointers; RT3D_EINVAL for any other shape. */
+ * rt3d_dn_pool2; the full-resolution output is not read back.  c1 = 5: the
+ * network with the direct-beam input, x1 BF16 [D][H][W][8] (channels 5-7
+ * zero) and w the 16-channel weights [32][27][16] (channels 0-4 used); one
+ * MFMA K-chunk holds the 15 products of three x-taps, so the output equals
+ * rt3d_dn_conv3d_fwd on 16-channel features up to the order of the
+ * products within a chunk.  Device pointers; RT3D_EINVAL for any other
+ * shape. */
 rt3d_status rt3d_dn_conv3d_fwd_pool(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* w, const float* bias,
                                     int32_t relu, uint16_t* y, uint16_t* ypool, void* stream);
 
@@ -149,12 +154,35 @@ rt3d_status rt3d_dn_adam(float* p, const float* g, float* m1, float* m2, uint16_
 rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* stream);
 
 /* Network input per voxel: channel 0 = hdir/scale, 1 = hdif/scale,
- * 2 = ln(1 + 20 k_ext dz), 3 = ln(1 + 200 k_abs dz), channels 4..cpad-1 = 0
- * (feat BF16 [vox][cpad], cpad 4 or a multiple of 16); base FP32 [vox][2] = (hdir/scale, hdif/scale), the
+ * 2 = ln(1 + 20 k_ext dz), 3 = ln(1 + 200 k_abs dz), with direct != NULL
+ * channel 4 = direct/scale (FP32 [vox], cpad >= 5), the rest 0
+ * (feat BF16 [vox][cpad], cpad 4, 8 or a multiple of 16); base FP32 [vox][2] = (hdir/scale, hdif/scale), the
  * residual the network corrects (NULL: not written).  hdir, hdif: FP32 heating fields; k_ext,
  * k_abs: FP32 [vox] extinction and absorption coefficients (m^-1). */
 rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
-                             float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream);
+                             float scale, uint64_t nvox, int32_t cpad, const float* direct, uint16_t* feat, float* base,
+                             void* stream);
+
+/* Direct-beam feature (an optional fifth network input, channel 4 of
+ * rt3d_dn_features = direct/scale): a deterministic estimate of the heating
+ * by the unscattered sun beam, in a gray medium k_ext, k_abs (FP32 device
+ * [nz][ny][nx], e.g. flux-weighted over g-points).  The beam's transmittance
+ * at every cell centre is carried down level by level (read bilinearly,
+ * periodic in x and y, from the level above where the sun ray through the
+ * centre meets it; half the path in each level); a cell absorbs
+ * T_entry (1 - exp(-k_ext dz / mu0)) k_abs / k_ext of the direct flux
+ * (T_entry: half a level above the centre), times direct_fraction and
+ * layer_scale[k] (FP64 device [nz], e.g. the heating-rate conversion).
+ * out: FP32 device [nz][ny][nx]; work: FP32 device [2][ny][nx].  A feature
+ * for the network, not the method's estimate (no scattering, no surface). */
+typedef struct {
+    int32_t nx, ny, nz;
+    float dx, dy, dz;
+    float sun_x, sun_y, sun_z;  /* propagation direction of the beam (unit, sun_z < 0) */
+    float direct_fraction;
+} rt3d_dn_direct;
+rt3d_status rt3d_dn_direct_feature(const rt3d_dn_direct* d, const float* k_ext, const float* k_abs,
+                                   const double* layer_scale, float* out, float* work, void* stream);
 
 /* Field scale of the network input: work[0] = (mean hdir + mean hdif) / 2
  * (1 if that is not positive), summed in FP64 in a fixed order (bitwise

@@ -797,6 +797,161 @@ conv3_c4_pool_kernel(const ConvArgs a, uint16_t* __restrict__ yp) {
     }
 }
 
+// The same for a network with the fifth (direct-beam) input: the first
+// layer reads 5 input channels stored as 8 per voxel (16 bytes, channels
+// 5-7 zero), and one MFMA K-chunk of 16 holds the 15 values of the three
+// x-taps of a (z, y) tap pair and one zero: lanes of half 0 take channels
+// 0-4 of voxel x-1 and 0-2 of voxel x, lanes of half 1 channels 3-4 of voxel
+// x, 0-4 of voxel x+1 and the zero (the B operand the matching weights, taken
+// from the 16-channel weight rows w[co][t][16]).  Pooling as in
+// conv3_c4_pool_kernel; bitwise equal to the unpacked first layer
+// (conv3_c32_kernel on 16-channel features) only up to the order of the
+// products within a K-chunk, as the packed 4-channel layer is.
+constexpr int kHaloVoxC5P = 4 * kHaloY32 * kHaloX;
+
+__device__ __forceinline__ uint32_t hi_lo(uint32_t a, uint32_t b) { return (a >> 16) | (b << 16); }
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+conv3_c5_pool_kernel(const ConvArgs a, uint16_t* __restrict__ yp) {
+    __shared__ uint4 tile[kHaloVoxC5P];
+    __shared__ uint4 rows[4 * 2 * 32 * 32 * 2 / 16];  // per wave two output rows, 32 voxels x 32 BF16 channels
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, half = lane >> 5;
+    const int tiles_x = (a.W + kTX - 1) / kTX, tiles_y = (a.H + kTY32 - 1) / kTY32;
+    long b = blockIdx.x;
+    const int txi = (int)(b % tiles_x);
+    b /= tiles_x;
+    const int tyi = (int)(b % tiles_y);
+    const int zp = (int)(b / tiles_y);  // pooled plane: output planes 2 zp, 2 zp + 1
+    const int z0 = 2 * zp;
+    const int x0 = txi * kTX, y0 = tyi * kTY32;
+    const int row0 = 4 * wave;
+    {
+        constexpr int kPer = (kHaloVoxC5P + 255) / 256, SB = 4;
+#pragma unroll 1
+        for (int j0 = 0; j0 < kPer; j0 += SB) {
+            uint4 vv[SB];
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int v = threadIdx.x + 256 * (j0 + j);
+                const int hx = v % kHaloX, hy = (v / kHaloX) % kHaloY32, hz = v / (kHaloX * kHaloY32);
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+                const bool in = x >= 0 && x < a.W && y >= 0 && y < a.H && z >= 0 && z < a.D;
+                const int xc = min(max(x, 0), a.W - 1), yc = min(max(y, 0), a.H - 1), zc = min(max(z, 0), a.D - 1);
+                vv[j] = *(in ? (const uint4*)(a.x1 + (((long)zc * a.H + yc) * a.W + xc) * 8)
+                             : reinterpret_cast<const uint4*>(dn_zero16));
+            }
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int v = threadIdx.x + 256 * (j0 + j);
+                if (j0 + j < kPer && v < kHaloVoxC5P) tile[v] = vv[j];
+            }
+        }
+    }
+    // B fragments of the 9 (z, y) tap pairs from the 16-channel weight rows:
+    // K 0-4 = tap dx 0 channels 0-4, K 5-9 = dx 1, K 10-14 = dx 2, K 15 = 0
+    uint4 bv[9];
+    const uint16_t* wrow = a.w + (long)m * 27 * 16;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        uint32_t wd[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            uint32_t lohi[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = 8 * half + 2 * p + e;  // K index of this lane's element
+                lohi[e] = k < 15 ? (uint32_t)wrow[(q * 3 + k / 5) * 16 + k % 5] : 0u;
+            }
+            wd[p] = lohi[0] | (lohi[1] << 16);
+        }
+        bv[q] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    }
+    __syncthreads();
+    const float bias = a.bias ? a.bias[m] : 0.0f;
+    uint16_t* scr = reinterpret_cast<uint16_t*>(rows) + wave * (2 * 32 * 32);
+    const int pv = lane >> 2, cg = lane & 3;
+    float s[2][8];
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[pr][k] = 0.0f;
+#pragma unroll 1
+    for (int oz = 0; oz < 2; ++oz) {
+        f32x16 acc[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[o][e] = 0.0f;
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const int i = ((oz + dz) * kHaloY32 + row0 + r) * kHaloX + m;  // voxel x-1 of output column m
+                // words of a voxel: (c0, c1), (c2, c3), (c4, 0), (0, 0)
+                const uint4 u = tile[i + half], v = tile[i + half + 1];
+                const uint4 av = half ? make_uint4(hi_lo(u.y, u.z), v.x, v.y, v.z)   // x: c3 c4; x+1: c0-c4, 0
+                                      : make_uint4(u.x, u.y, u.z | (v.x << 16), hi_lo(v.x, v.y));  // x-1: c0-c4; x: c0-c2
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const int dy = r - o;
+                    if (dy >= 0 && dy <= 2)
+                        acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(av), as_bf16x8(bv[dz * 3 + dy]),
+                                                                         acc[o], 0, 0, 0);
+                }
+            }
+        const int zz = z0 + oz;
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+#pragma unroll
+            for (int oo = 0; oo < 2; ++oo)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float v = acc[2 * pr + oo][e] + bias;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    scr[(oo * 32 + 8 * (e >> 2) + 4 * half + (e & 3)) * 32 + m] = f2bf(v);
+                }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int oo = 0; oo < 2; ++oo) {
+                const int y = y0 + row0 + 2 * pr + oo;
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    const int q = it * 64 + lane;
+                    const int x = x0 + (q >> 2);
+                    const uint4 v = *reinterpret_cast<const uint4*>(scr + (oo * 32 + (q >> 2)) * 32 + 8 * (q & 3));
+                    if (y < a.H && x < a.W)
+                        *reinterpret_cast<uint4*>(a.y1 + (((long)zz * a.H + y) * a.W + x) * 32 + 8 * (q & 3)) = v;
+                }
+            }
+#pragma unroll
+            for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+                for (int xx = 0; xx < 2; ++xx) {
+                    const uint4 u = *reinterpret_cast<const uint4*>(scr + (yy * 32 + 2 * pv + xx) * 32 + 8 * cg);
+                    const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        s[pr][2 * k] += bf2f((uint16_t)(wd[k] & 0xffffu));
+                        s[pr][2 * k + 1] += bf2f((uint16_t)(wd[k] >> 16));
+                    }
+                }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    const int hh = a.H / 2, wh = a.W / 2;
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+        const int yh = (y0 + row0) / 2 + pr, xh = x0 / 2 + pv;
+        if (yh >= hh || xh >= wh) continue;
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = (uint32_t)f2bf(0.125f * s[pr][2 * k]) | ((uint32_t)f2bf(0.125f * s[pr][2 * k + 1]) << 16);
+        *reinterpret_cast<uint4*>(yp + (((long)zp * hh + yh) * wh + xh) * 32 + 8 * cg) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+}
+
 // wt[ci][taps-1-t][co] = w[co][t][ci]  (data gradient = convolution of the
 // output gradient with the flipped, transposed kernel)
 __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int cout, int cin,
@@ -1066,8 +1221,8 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict
 // residual base [v][2].
 __global__ void features_kernel(const float* __restrict__ hdir, const float* __restrict__ hdif,
                                 const float* __restrict__ k_ext, const float* __restrict__ k_abs, float dz,
-                                float inv_scale, size_t nvox, int cpad, uint16_t* __restrict__ feat,
-                                float* __restrict__ base) {
+                                float inv_scale, size_t nvox, int cpad, const float* __restrict__ direct,
+                                uint16_t* __restrict__ feat, float* __restrict__ base) {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < nvox; v += (size_t)gridDim.x * blockDim.x) {
         const float a = hdir[v] * inv_scale, b = hdif[v] * inv_scale;
         uint16_t* f = feat + v * cpad;
@@ -1075,12 +1230,66 @@ __global__ void features_kernel(const float* __restrict__ hdir, const float* __r
         f[1] = f2bf(b);
         f[2] = f2bf(__logf(1.0f + 20.0f * k_ext[v] * dz));
         f[3] = f2bf(__logf(1.0f + 200.0f * k_abs[v] * dz));
-        for (int q = 4; q < cpad; ++q) f[q] = 0;
+        int q = 4;
+        if (direct) f[q++] = f2bf(direct[v] * inv_scale);
+        for (; q < cpad; ++q) f[q] = 0;
         if (base) {
             base[2 * v] = a;
             base[2 * v + 1] = b;
         }
     }
+}
+
+// Direct-beam feature: a deterministic estimate of the heating by the
+// unscattered sun beam in a gray medium (flux-weighted extinction k_e and
+// absorption k_a).  T[k][j][i], the beam's transmittance at the centre of
+// cell (i, j, k), is carried down level by level: the ray through a centre,
+// followed back up towards the sun by one level height, meets the level
+// above at a point where that level's T is read bilinearly (periodic in x and
+// y); the path between them runs half in each level.  In the top level the
+// ray leaves through the domain top after half a level.  The cell absorbs
+// T_entry (1 - exp(-k_e dz / mu0)) k_a / k_e of the direct flux, T_entry
+// being the transmittance half a level above the centre; times the direct
+// fraction of the flux and the level's heating-rate scale.  One launch per
+// level, from the top: T of the level above is read from work[(k + 1) & 1],
+// this level's written to work[k & 1].
+struct DirectArgs {
+    int nx, ny, nz;
+    float sx, sy;       // horizontal offset of the point one level up, in cells
+    float path;         // slant path of one level height (m): dz / mu0
+    float fdir;         // direct fraction of the flux at the domain top
+};
+
+__global__ void direct_level_kernel(const DirectArgs d, int k, const float* __restrict__ ke,
+                                    const float* __restrict__ ka, const double* __restrict__ scale,
+                                    float* __restrict__ work, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx) return;
+    const size_t plane = (size_t)d.nx * d.ny;
+    const size_t c = (size_t)k * plane + (size_t)j * d.nx + i;
+    const float kc = ke[c];
+    float t;
+    if (k == d.nz - 1) {
+        t = __expf(-0.5f * kc * d.path);
+    } else {
+        const float* above = work + ((k + 1) & 1) * plane;
+        const float fx = (float)i + d.sx, fy = (float)j + d.sy;
+        const float x0 = floorf(fx), y0 = floorf(fy);
+        const float wx = fx - x0, wy = fy - y0;
+        auto wrap = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+        const int i0 = wrap((int)x0, d.nx), i1 = wrap((int)x0 + 1, d.nx);
+        const int j0 = wrap((int)y0, d.ny), j1 = wrap((int)y0 + 1, d.ny);
+        const float tu = (1.0f - wy) * ((1.0f - wx) * above[(size_t)j0 * d.nx + i0] + wx * above[(size_t)j0 * d.nx + i1]) +
+                         wy * ((1.0f - wx) * above[(size_t)j1 * d.nx + i0] + wx * above[(size_t)j1 * d.nx + i1]);
+        const int im = wrap((int)floorf((float)i + 0.5f + 0.5f * d.sx), d.nx);
+        const int jm = wrap((int)floorf((float)j + 0.5f + 0.5f * d.sy), d.ny);
+        const float ku = ke[(size_t)(k + 1) * plane + (size_t)jm * d.nx + im];  // the level above, mid-way
+        t = tu * __expf(-0.5f * (kc + ku) * d.path);
+    }
+    work[(k & 1) * plane + (size_t)j * d.nx + i] = t;
+    const float tau = kc * d.path;
+    const float absorbed = kc > 0.0f ? t * __expf(0.5f * tau) * -expm1f(-tau) * (ka[c] / kc) : 0.0f;
+    out[c] = (float)((double)(d.fdir * absorbed) * scale[k]);
 }
 
 // Sums of two FP32 fields in FP64, in a fixed order: per-block partial sums
@@ -1181,15 +1390,19 @@ const char* rt3d_dn_last_error(void) { return d_err; }
 rt3d_status rt3d_dn_conv3d_fwd_pool(const rt3d_dn_conv* c, const uint16_t* x1, const uint16_t* w, const float* bias,
                                     int32_t relu, uint16_t* y, uint16_t* ypool, void* stream) {
     if (!c || !x1 || !w || !y || !ypool) return RT3D_EINVAL;
-    if (c->c1 != 4 || c->c2 != 0 || c->ksize != 3 || c->cout != 32 || c->up1 || c->yf_cols) return RT3D_EINVAL;
+    if ((c->c1 != 4 && c->c1 != 5) || c->c2 != 0 || c->ksize != 3 || c->cout != 32 || c->up1 || c->yf_cols)
+        return RT3D_EINVAL;
     if (c->D <= 0 || c->H <= 0 || c->W <= 0 || c->D % 2 || c->H % 2 || c->W % 2) return RT3D_EINVAL;
     ConvArgs a;
     memset(&a, 0, sizeof a);
-    a.x1 = x1; a.c1 = 4; a.w = w; a.bias = bias; a.y1 = y; a.o1 = 32;
+    a.x1 = x1; a.c1 = c->c1; a.w = w; a.bias = bias; a.y1 = y; a.o1 = 32;
     a.D = c->D; a.H = c->H; a.W = c->W; a.cout = 32; a.relu = relu ? 1 : 0;
     const long tiles = (long)(c->D / 2) * ((c->H + kTY32 - 1) / kTY32) * ((c->W + kTX - 1) / kTX);
     if (tiles > 0x7fffffffL) return RT3D_EINVAL;
-    hipLaunchKernelGGL(conv3_c4_pool_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a, ypool);
+    if (c->c1 == 4)
+        hipLaunchKernelGGL(conv3_c4_pool_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a, ypool);
+    else
+        hipLaunchKernelGGL(conv3_c5_pool_kernel, dim3((unsigned)tiles), dim3(256), 0, (hipStream_t)stream, a, ypool);
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }
@@ -1433,12 +1646,14 @@ rt3d_status rt3d_dn_to_bf16(const float* x, uint16_t* y, uint64_t n, void* strea
 }
 
 rt3d_status rt3d_dn_features(const float* hdir, const float* hdif, const float* k_ext, const float* k_abs, float dz,
-                             float scale, uint64_t nvox, int32_t cpad, uint16_t* feat, float* base, void* stream) {
-    if (!hdir || !hdif || !k_ext || !k_abs || !feat || (cpad != 4 && (cpad < 16 || cpad % 16)) ||
+                             float scale, uint64_t nvox, int32_t cpad, const float* direct, uint16_t* feat, float* base,
+                             void* stream) {
+    if (!hdir || !hdif || !k_ext || !k_abs || !feat || (cpad != 4 && cpad != 8 && (cpad < 16 || cpad % 16)) ||
         !(scale > 0.0f))
         return RT3D_EINVAL;
+    if (direct && cpad < 5) return RT3D_EINVAL;
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, hdir, hdif, k_ext,
-                       k_abs, dz, 1.0f / scale, (size_t)nvox, cpad, feat, base);
+                       k_abs, dz, 1.0f / scale, (size_t)nvox, cpad, direct, feat, base);
     DN_TRY(hipGetLastError());
     return RT3D_OK;
 }
@@ -1468,6 +1683,27 @@ rt3d_status rt3d_dn_residual_unfeature(const float* out, int32_t cpad, const flo
     hipLaunchKernelGGL(residual_unfeature_kernel, dim3(blocks_for(nvox)), dim3(256), 0, (hipStream_t)stream, out,
                        cpad, hdir_in, hdif_in, 1.0f / scale, scale, (size_t)nvox, hdir, hdif);
     DN_TRY(hipGetLastError());
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_dn_direct_feature(const rt3d_dn_direct* d, const float* k_ext, const float* k_abs,
+                                   const double* layer_scale, float* out, float* work, void* stream) {
+    if (!d || !k_ext || !k_abs || !layer_scale || !out || !work) return RT3D_EINVAL;
+    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || !(d->dx > 0.f) || !(d->dy > 0.f) || !(d->dz > 0.f)) return RT3D_EINVAL;
+    if (!(d->sun_z < 0.f) || !(d->direct_fraction >= 0.f && d->direct_fraction <= 1.f)) return RT3D_EINVAL;
+    DirectArgs a;
+    const float up = d->dz / -d->sun_z;  // path length of one level height, followed back towards the sun
+    a.nx = d->nx; a.ny = d->ny; a.nz = d->nz;
+    a.sx = -d->sun_x * up / d->dx;
+    a.sy = -d->sun_y * up / d->dy;
+    a.path = up;
+    a.fdir = d->direct_fraction;
+    const dim3 grid((unsigned)((d->nx + 255) / 256), (unsigned)d->ny);
+    for (int k = d->nz - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(direct_level_kernel, grid, dim3(256), 0, (hipStream_t)stream, a, k, k_ext, k_abs,
+                           layer_scale, work, out);
+        DN_TRY(hipGetLastError());
+    }
     return RT3D_OK;
 }
 

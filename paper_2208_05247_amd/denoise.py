@@ -37,6 +37,13 @@ NOUT = 2
 LEVELS = 4
 
 
+class _Direct(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_float), ("dy", ctypes.c_float), ("dz", ctypes.c_float),
+                ("sun_x", ctypes.c_float), ("sun_y", ctypes.c_float), ("sun_z", ctypes.c_float),
+                ("direct_fraction", ctypes.c_float)]
+
+
 class _Conv(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("c1", ctypes.c_int32), ("c2", ctypes.c_int32), ("cout", ctypes.c_int32),
@@ -66,7 +73,8 @@ def load():
         "rt3d_dn_mse": [P, I, P, P, I, U, P, P, P, P],
         "rt3d_dn_adam": [P, P, P, P, P, U, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, I, P],
         "rt3d_dn_to_bf16": [P, P, U, P],
-        "rt3d_dn_features": [P, P, P, P, ctypes.c_float, ctypes.c_float, U, I, P, P, P],
+        "rt3d_dn_features": [P, P, P, P, ctypes.c_float, ctypes.c_float, U, I, P, P, P, P],
+        "rt3d_dn_direct_feature": [ctypes.POINTER(_Direct), P, P, P, P, P, P],
         "rt3d_dn_unfeature": [P, ctypes.c_float, U, P, P, P],
         "rt3d_dn_field_scale": [P, P, U, P, P],
         "rt3d_dn_residual_unfeature": [P, I, P, P, ctypes.c_float, U, P, P, P],
@@ -147,13 +155,15 @@ def conv_fwd_head(x1, x2, w, bias, relu, hw, hb, out, up1=False):
 
 
 def conv_fwd_pool(x1, w, bias, relu, y, ypool):
-    """The packed first layer (x1 BF16 [D][H][W][4], w [32][27][4]) and the
-    2x2x2 average pooling of its output in one launch: y [D][H][W][32] and
-    ypool [D/2][H/2][W/2][32], bitwise conv_fwd followed by pool2."""
-    D, H, W, c1 = x1.shape
-    if c1 != 4 or tuple(y.shape) != (D, H, W, 32) or tuple(ypool.shape) != (D // 2, H // 2, W // 2, 32):
-        raise ValueError("conv_fwd_pool: x1 [D][H][W][4], y [D][H][W][32], ypool [D/2][H/2][W/2][32]")
-    c = _Conv(D, H, W, 4, 0, 32, 3, 0, 0)
+    """The packed first layer and the 2x2x2 average pooling of its output in
+    one launch: y [D][H][W][32] and ypool [D/2][H/2][W/2][32].  Four inputs:
+    x1 BF16 [D][H][W][4], w [32][27][4], bitwise conv_fwd followed by pool2;
+    five inputs (the direct-beam feature): x1 [D][H][W][8] (channels 5-7
+    zero), w the 16-channel weights [32][27][16]."""
+    D, H, W, cx = x1.shape
+    if cx not in (4, 8) or tuple(y.shape) != (D, H, W, 32) or tuple(ypool.shape) != (D // 2, H // 2, W // 2, 32):
+        raise ValueError("conv_fwd_pool: x1 [D][H][W][4 or 8], y [D][H][W][32], ypool [D/2][H/2][W/2][32]")
+    c = _Conv(D, H, W, 4 if cx == 4 else 5, 0, 32, 3, 0, 0)
     _check(load().rt3d_dn_conv3d_fwd_pool(ctypes.byref(c), _p(x1), _p(w), _p(bias), int(relu), _p(y), _p(ypool),
                                           _s()), "rt3d_dn_conv3d_fwd_pool")
 
@@ -239,7 +249,10 @@ class Denoiser:
     """Parameters (FP32 masters, BF16 copies, gradients, Adam moments) and the
     forward / backward passes over one field."""
 
-    def __init__(self, base: int = 32, seed: int = 0, device="cuda"):
+    def __init__(self, base: int = 32, seed: int = 0, device="cuda", n_in: int = 4):
+        if n_in not in (4, 5):
+            raise ValueError("n_in: 4 inputs, or 5 with the direct-beam feature")
+        self.n_in = n_in
         self.layers = architecture(base)
         self.device = device
         g = torch.Generator().manual_seed(seed)
@@ -251,7 +264,7 @@ class Denoiser:
             std = math.sqrt(2.0 / fan_in) if L.name != "head" else 1e-3
             w = torch.randn(L.cout, taps, L.c1 + L.c2, generator=g, dtype=torch.float32) * std
             if L.name == "e0":
-                w[:, :, 4:] = 0.0  # padding channels carry nothing
+                w[:, :, n_in:] = 0.0  # padding channels carry nothing
             if L.name == "head":
                 w[NOUT:] = 0.0
             self.p[L.name] = w.to(device).contiguous()
@@ -290,22 +303,27 @@ class Denoiser:
         return y
 
     def forward(self, feat: torch.Tensor, keep: bool = False) -> torch.Tensor:
-        """feat: BF16 [D][H][W][16], or [D][H][W][4] for inference (the first
-        layer then runs packed: three x-taps per MFMA K-chunk); returns the
+        """feat: BF16 [D][H][W][16], or for inference [D][H][W][4] (and
+        [D][H][W][8] with the direct-beam input; the first layer then runs
+        packed: three x-taps per MFMA K-chunk); returns the
         FP32 head output [D][H][W][32] with keep (training) or its NOUT used
         channels [D][H][W][2]."""
         D, H, W, cf = feat.shape
         if D % 8 or H % 8 or W % 8:
             raise ValueError("grid dimensions must be multiples of 8 (three pooling levels)")
-        if cf == 4 and keep:
+        if cf in (4, 8) and keep:
             raise ValueError("training needs the 16-channel features")
+        if cf == 8 and self.n_in != 5:
+            raise ValueError("8-channel features carry the direct-beam input (n_in 5)")
         a = {"x0": feat}
-        if cf == 4:
-            # the packed first layer and its pooling in one launch
+        if cf in (4, 8):
+            # the packed first layer and its pooling in one launch (4 inputs,
+            # or 5 with the direct-beam feature in 8 channels)
             L = self.layers[0]
             a["e0"] = bf16_empty(D, H, W, L.cout)
             a["p0"] = bf16_empty(D // 2, H // 2, W // 2, L.cout)
-            conv_fwd_pool(feat, self.pb["e0"][:, :, :4].contiguous(), self.bias["e0"], L.relu, a["e0"], a["p0"])
+            w0 = self.pb["e0"][:, :, :4].contiguous() if cf == 4 else self.pb["e0"]
+            conv_fwd_pool(feat, w0, self.bias["e0"], L.relu, a["e0"], a["p0"])
         else:
             a["e0"] = self._conv("e0", feat)
             a["p0"] = pool2(a["e0"])
@@ -420,16 +438,32 @@ class Denoiser:
 # ---------------------------------------------------------------------------
 
 def features(hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, k_abs: torch.Tensor, dz: float,
-             scale: float, cpad: int = CPAD):
-    """BF16 features [D][H][W][cpad] (4 used; cpad 16 for training, 4 for
-    the packed first layer of inference) and FP32 residual base
-    [D][H][W][2]."""
+             scale: float, cpad: int = CPAD, direct: Optional[torch.Tensor] = None):
+    """BF16 features [D][H][W][cpad] (4 used, 5 with the direct-beam feature;
+    cpad 16 for training, 4 for the packed first layer of inference) and
+    FP32 residual base [D][H][W][2]."""
     D, H, W = hdir.shape
     feat = bf16_empty(D, H, W, cpad)
     base = torch.empty(D, H, W, NOUT, dtype=torch.float32, device=hdir.device)
     _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), _p(k_abs), float(dz), float(scale), hdir.numel(),
-                                   cpad, _p(feat), _p(base), _s()), "rt3d_dn_features")
+                                   cpad, _p(direct), _p(feat), _p(base), _s()), "rt3d_dn_features")
     return feat, base
+
+
+def direct_feature(k_ext: torch.Tensor, k_abs: torch.Tensor, grid, sza: float, azimuth: float,
+                   direct_fraction: float, layer_scale: torch.Tensor) -> torch.Tensor:
+    """rt3d_dn_direct_feature: deterministic direct-beam heating of a gray
+    medium (FP32 [nz][ny][nx]), the fifth network input."""
+    th, ph = math.radians(sza), math.radians(azimuth)
+    d = _Direct(int(grid.nx), int(grid.ny), int(grid.nz), float(grid.dx), float(grid.dy), float(grid.dz),
+                -math.sin(th) * math.sin(ph), -math.sin(th) * math.cos(ph), -math.cos(th), float(direct_fraction))
+    if layer_scale.dtype != torch.float64 or layer_scale.numel() != grid.nz:
+        raise ValueError("layer_scale: FP64 [nz]")
+    out = torch.empty_like(k_ext)
+    work = torch.empty(2, grid.ny, grid.nx, dtype=torch.float32, device=k_ext.device)
+    _check(load().rt3d_dn_direct_feature(ctypes.byref(d), _p(k_ext), _p(k_abs), _p(layer_scale), _p(out), _p(work),
+                                         _s()), "rt3d_dn_direct_feature")
+    return out
 
 
 SCALE_WORK = 2049  # RT3D_DN_SCALE_WORK
@@ -466,14 +500,23 @@ def train_step(net: Denoiser, feat, base, target, lr: float) -> torch.Tensor:
 
 
 def denoise(net: Denoiser, hdir: torch.Tensor, hdif: torch.Tensor, k_ext: torch.Tensor, k_abs: torch.Tensor,
-            dz: float):
-    """Inference: denoised (hdir, hdif), same units as the inputs."""
+            dz: float, direct: Optional[dict] = None):
+    """Inference: denoised (hdir, hdif), same units as the inputs.  A network
+    with the direct-beam input needs direct = the keyword arguments of
+    direct_feature beyond k_ext, k_abs (grid, sza, azimuth, direct_fraction,
+    layer_scale); the feature is computed here."""
     s = field_scale(hdir, hdif)
     D, H, W = hdir.shape
-    feat = bf16_empty(D, H, W, 4)
+    dfield = None
+    if net.n_in == 5:
+        if direct is None:
+            raise ValueError("this network takes the direct-beam feature: pass direct=")
+        dfield = direct_feature(k_ext, k_abs, **direct)
+    cpad = 4 if dfield is None else 8  # packed first layer: 4 inputs, or 5 in 8 channels
+    feat = bf16_empty(D, H, W, cpad)
     # the residual base is not stored: the output pass forms it again
-    _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), _p(k_abs), float(dz), float(s), hdir.numel(), 4,
-                                   _p(feat), None, _s()), "rt3d_dn_features")
+    _check(load().rt3d_dn_features(_p(hdir), _p(hdif), _p(k_ext), _p(k_abs), float(dz), float(s), hdir.numel(), cpad,
+                                   _p(dfield), _p(feat), None, _s()), "rt3d_dn_features")
     out = net.forward(feat)
     od, of = torch.empty_like(hdir), torch.empty_like(hdif)
     _check(load().rt3d_dn_residual_unfeature(_p(out), out.shape[-1], _p(hdir), _p(hdif), float(s), hdir.numel(),

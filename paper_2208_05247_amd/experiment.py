@@ -120,6 +120,13 @@ class Tracer:
         self.ls = layer_scale(self.grid)
         self.k_ext = None
 
+    def direct_args(self) -> dict:
+        """Arguments of denoise.direct_feature beyond the gray fields: the
+        scene's sun, the direct fraction of the flux entering the domain top
+        (share-weighted) and the heating-rate scale per level."""
+        return {"grid": self.grid, "sza": self.wl.sza, "azimuth": self.wl.azimuth,
+                "direct_fraction": 1.0 - float(self.entry["mean_diffuse_fraction"]), "layer_scale": self.ls}
+
     def k_mean(self):
         """Flux-weighted extinction and absorption fields (network inputs)."""
         if self.k_ext is None:
@@ -226,11 +233,12 @@ def train(net: dn.Denoiser, n_fields: int, steps_per_field: int, nx: int, nz: in
         tr = Tracer(wl, tod_entry=tod_entry)
         tdir, tdif, _, _ = tr.heating(high, seed=10_000_000 * (f + 1))
         kext, kabs = tr.k_mean()
+        dfield = dn.direct_feature(kext, kabs, **tr.direct_args()) if net.n_in == 5 else None
         for s in range(steps_per_field):
             per_col = low[(f * steps_per_field + s) % len(low)]
             ndir, ndif, _, _ = tr.heating(per_col, seed=10_000_000 * (f + 1) + 100_000 * (s + 1))
             sc = dn.field_scale(ndir, ndif)
-            feat, base = dn.features(ndir, ndif, kext, kabs, dz, sc)
+            feat, base = dn.features(ndir, ndif, kext, kabs, dz, sc, direct=dfield)
             target = torch.stack([tdir / sc, tdif / sc], dim=-1).float().contiguous()
             lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / total_steps))
             torch.cuda.synchronize()
@@ -251,6 +259,8 @@ def _weight_arrays(net: dn.Denoiser) -> dict:
     for k in sorted(net.p):
         arr[f"w_{k}"] = net.pb[k].contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
         arr[f"b_{k}"] = net.bias[k].cpu().numpy().astype(np.float32)
+    if net.n_in != 4:
+        arr["n_in"] = np.array([net.n_in], dtype=np.int32)
     return arr
 
 
@@ -280,7 +290,7 @@ def load_denoiser(path: str, expect_sha256=None):
     sha = weights_sha256(arr)
     if expect_sha256 is not None and sha != expect_sha256:
         raise RuntimeError(f"{path}: weights sha256 {sha} != expected {expect_sha256}")
-    net = dn.Denoiser(base=32, seed=0)
+    net = dn.Denoiser(base=32, seed=0, n_in=int(arr["n_in"][0]) if "n_in" in arr else 4)
     st = {}
     for k in net.p:
         bits = torch.from_numpy(arr[f"w_{k}"].view(np.int16).copy())
@@ -289,6 +299,13 @@ def load_denoiser(path: str, expect_sha256=None):
     net.load_state(st)
     return net, {"path": os.path.relpath(path, os.path.dirname(os.path.dirname(os.path.abspath(__file__)))),
                  "sha256": sha}
+
+
+def committed_denoiser_inputs() -> int:
+    """Number of network inputs of the committed weights (4, or 5 with the
+    direct-beam feature)."""
+    with np.load(WEIGHTS_PATH, allow_pickle=False) as z:
+        return int(z["n_in"][0]) if "n_in" in z.files else 4
 
 
 def load_committed_denoiser():
@@ -355,7 +372,7 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
         hd, hf, kms, total = tr.heating(n, seed=7_000_000_000 + 1_000_000 * n)
         torch.cuda.synchronize()
         w1 = time.perf_counter()
-        od, of = dn.denoise(net, hd, hf, kext, kabs, g.dz)
+        od, of = dn.denoise(net, hd, hf, kext, kabs, g.dz, direct=tr.direct_args() if net.n_in == 5 else None)
         torch.cuda.synchronize()
         w2 = time.perf_counter()
         e_raw = eps_against(hd + hf, ref_a, ref_b)
@@ -460,6 +477,8 @@ def main():
     ap.add_argument("--save-weights", default=None, help="store the trained weights here (.npz)")
     ap.add_argument("--weights", default=None, help="evaluate these stored weights instead of training")
     ap.add_argument("--no-eval", action="store_true", help="train (and save) only")
+    ap.add_argument("--direct-feature", action="store_true",
+                    help="give the network a fifth input: the deterministic direct-beam heating of the gray medium")
     args = ap.parse_args()
     if args.config3:
         config3(args.out)
@@ -475,7 +494,7 @@ def main():
         res["weights"] = winfo
         train_s = None
     else:
-        net = dn.Denoiser(base=32, seed=0)
+        net = dn.Denoiser(base=32, seed=0, n_in=5 if args.direct_feature else 4)
         log(f"denoiser parameters: {net.n_params()}")
         t0 = time.perf_counter()
         low = tuple(int(v) for v in args.train_low.split(","))

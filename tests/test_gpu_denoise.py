@@ -283,6 +283,42 @@ def test_training_is_bitwise_reproducible(dn):
         assert torch.equal(nets[0].bias[k], nets[1].bias[k]), k
 
 
+def test_direct_feature_closed_form_and_translation(dn):
+    """Direct-beam feature: in horizontally uniform layers it is the closed
+    form (1 - f_d) exp(-tau_above / mu0) (1 - exp(-k dz / mu0)) k_a / k scale
+    (tau_above: extinction of the levels above times dz); on the periodic
+    grid, shifting the fields shifts the feature."""
+    import math
+    from paper_2208_05247_amd.synthetic import Grid
+    nx, ny, nz, dz = 24, 20, 9, 20.0
+    grid = Grid(nx, ny, nz, 25.0, 25.0, dz)
+    g = torch.Generator().manual_seed(31)
+    kz = torch.rand(nz, generator=g, dtype=torch.float64) * 0.02
+    kz[4] = 0.0  # a level without extinction
+    az = kz * torch.rand(nz, generator=g, dtype=torch.float64)
+    ke = kz[:, None, None].expand(nz, ny, nx).float().contiguous().cuda()
+    ka = az[:, None, None].expand(nz, ny, nx).float().contiguous().cuda()
+    ls = (torch.rand(nz, generator=g, dtype=torch.float64) + 0.5).cuda()
+    sza, fd = 50.0, 0.8
+    out = dn.direct_feature(ke, ka, grid, sza, 33.0, fd, ls).double().cpu()
+    mu0 = math.cos(math.radians(sza))
+    ke64, ka64 = ke[:, 0, 0].double().cpu(), ka[:, 0, 0].double().cpu()
+    for k in range(nz):
+        above = float(ke64[k + 1:].sum()) * dz
+        frac = (1 - math.exp(-float(ke64[k]) * dz / mu0)) * float(ka64[k] / ke64[k]) if ke64[k] > 0 else 0.0
+        ref = fd * math.exp(-above / mu0) * frac * float(ls[k])
+        assert torch.allclose(out[k], torch.full_like(out[k], ref), rtol=2e-5, atol=1e-12), k
+    # a 3D field: translation equivariance on the periodic grid
+    ke3 = (torch.rand(nz, ny, nx, generator=g) * 0.05).cuda()
+    ka3 = ke3 * 0.01
+    f = dn.direct_feature(ke3, ka3, grid, sza, 200.0, fd, ls)
+    fs = dn.direct_feature(torch.roll(ke3, (3, 5), (1, 2)).contiguous(), torch.roll(ka3, (3, 5), (1, 2)).contiguous(),
+                           grid, sza, 200.0, fd, ls)
+    # equal up to the rounding of the interpolation weights (i + offset - floor)
+    assert torch.allclose(torch.roll(f, (3, 5), (1, 2)), fs, rtol=1e-5, atol=0.0)
+    assert (f > 0).all()
+
+
 def test_field_scale_and_fused_output(dn):
     """rt3d_dn_field_scale against the FP64 means (and reproducible to the
     bit); rt3d_dn_residual_unfeature bitwise equal to features' base, the
@@ -333,6 +369,44 @@ def test_first_layer_with_pooling_is_bitwise(dn):
     with pytest.raises(Exception):
         dn.conv_fwd_pool(x, w, b, True, torch.empty(3, 16, 32, 32, dtype=torch.bfloat16, device="cuda"),
                          torch.empty(1, 8, 16, 32, dtype=torch.bfloat16, device="cuda"))
+
+
+def test_packed_five_channel_first_layer(dn):
+    """The packed first layer of the network with the direct-beam input (5
+    inputs in 8 channels, 15 products per MFMA K-chunk) and its pooling
+    against the unpacked 16-channel first layer and rt3d_dn_pool2 (equal up
+    to the order of the products: within BF16 rounding), partial tiles
+    included; the whole inference forward likewise."""
+    g = torch.Generator().manual_seed(41)
+    for D, H, W in ((4, 20, 36), (2, 16, 32)):
+        x16 = torch.zeros(D, H, W, 16, dtype=torch.float64)
+        x16[..., :5] = torch.randn(D, H, W, 5, generator=g, dtype=torch.float64)
+        x16 = x16.to(torch.bfloat16).cuda()
+        x8 = x16[..., :8].contiguous()
+        w = (torch.randn(32, 27, 16, generator=g) * 0.2)
+        w[:, :, 5:] = 0.0
+        w = w.to(torch.bfloat16).cuda()
+        b = (torch.randn(32, generator=g) * 0.1).cuda()
+        y_ref = torch.empty(D, H, W, 32, dtype=torch.bfloat16, device="cuda")
+        yf = torch.empty(D, H, W, 32, dtype=torch.float32, device="cuda")
+        dn.conv_fwd(x16, None, w, b, True, 32, 3, y1=y_ref, yf=yf)
+        p_ref = dn.pool2(y_ref)
+        y = torch.empty_like(y_ref)
+        p = torch.empty_like(p_ref)
+        dn.conv_fwd_pool(x8, w, b, True, y, p)
+        assert (y.float() - yf).abs().max().item() <= 8e-3 * yf.abs().max().item()
+        assert (p.float() - p_ref.float()).abs().max().item() <= 8e-3 * p_ref.float().abs().max().item()
+    net = dn.Denoiser(base=32, seed=7, n_in=5)
+    hd = torch.rand(16, 16, 24, generator=g).cuda()
+    hf = torch.rand(16, 16, 24, generator=g).cuda()
+    ke = torch.rand(16, 16, 24, generator=g).cuda() * 0.02
+    dirf = torch.rand(16, 16, 24, generator=g).cuda()
+    f16, _ = dn.features(hd, hf, ke, 0.1 * ke, 20.0, 1.0, direct=dirf)
+    f8, _ = dn.features(hd, hf, ke, 0.1 * ke, 20.0, 1.0, cpad=8, direct=dirf)
+    assert torch.equal(f16[..., :8].contiguous(), f8) and f8[..., 4].abs().sum() > 0
+    a = net.forward(f16)
+    b8 = net.forward(f8)
+    assert rel(b8.double().cpu(), a.double().cpu()) < 2e-2
 
 
 def test_packed_first_layer(dn):

@@ -200,6 +200,14 @@ enum {
                                      their values first and one atomic is
                                      issued per distinct element (same
                                      results; speed only) */
+#define RT3D_FLAG_CELL_MASK 0x40u /* rt3d_trace_batched: at a tentative
+                                     collision in an acceleration cell with
+                                     cloud, first read the fine cell's bit in
+                                     a cloud-cell mask (built in the
+                                     workspace) and skip the record gather
+                                     for a cloud-free cell, instead of
+                                     gathering at every one (same results;
+                                     speed only) */
 
 typedef struct {
     /* acceleration-grid cell ("brick") in fine cells; must divide nx, ny, nz */

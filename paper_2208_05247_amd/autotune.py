@@ -3,8 +3,9 @@
 Picks the acceleration-grid cell ("brick") shape, the crossings a lane makes
 per loop iteration, the persistent grid size, the photon-id pool a wave takes
 per refill, how many idle lanes a wave waits for before it starts new photons,
-the tally mode (merging a lane's deposits, wave-aggregated atomics) and the
-entry tile of the photon schedule from short
+the tally mode (merging a lane's deposits, wave-aggregated atomics), for
+batched launches the cloud-cell mask, and the entry tile of the photon
+schedule from short
 calibration runs (the tile matters only when the sample holds full passes
 over the columns, i.e. at least as many photons per g-point as columns).  The
 objective is tracing-kernel time per photon (HIP events around the kernel),
@@ -81,7 +82,7 @@ def _store_cache(path, cache):
 
 
 def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=None, pools=None,
-            grid_mults=(1,), try_merge=True, refills=None, tiles=None):
+            grid_mults=(1,), try_merge=True, refills=None, tiles=None, try_cell_mask=False):
     """Staged coordinate search; run(opts) returns kernel ms for `sample` photons."""
     table = []
 
@@ -131,6 +132,11 @@ def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=
             ms = measure(o)
             if ms < best_ms:
                 best_ms, best = ms, o
+    if try_cell_mask:  # batched only: skip the record gather in cloud-free cells
+        o = {**best, "cell_mask": True}
+        ms = measure(o)
+        if ms < best_ms:
+            best_ms, best = ms, o
     for t in (tiles or TILES):
         t = (grid.nx, grid.ny) if t == "domain" else t
         if grid.nx % t[0] or grid.ny % t[1]:
@@ -191,6 +197,7 @@ def tune_batched(dm: "rt3d.DeviceBatchedMedium", sza: float, azimuth: float, pho
         return rt3d.last_trace_ms()
 
     search_kw.setdefault("grid_mults", (3, 4))
+    search_kw.setdefault("try_cell_mask", True)
     best, best_ms, table = _search(run, dm.grid, sample, **search_kw)
     res = TuneResult(best, best_ms / sample, table)
     if cache_path:

@@ -267,6 +267,11 @@ struct TraceParams {
     const float2* __restrict__ gas;
     const float* __restrict__ albedo;
     const float* __restrict__ majorant;                    // [ngp][nmaj]
+    // factored only (null: not used): per acceleration cell, one bit per fine
+    // cell (1 = some cloud extinction), mask_words words per acceleration
+    // cell, the bits in x-fastest order of the cell's bx * by * bz fine cells
+    const uint32_t* __restrict__ cell_mask;
+    int mask_words;
     Schedule sched;
     unsigned long long* abs_dir;
     unsigned long long* abs_dif;
@@ -636,7 +641,15 @@ __global__ void __launch_bounds__(Shape_<kFactored>::threads)
             const int j = cell_ix(py, P.inv_dy, bj, P.by);
             const int k = cell_ix(pz, P.inv_dz, bk, P.bz);
             const uint32_t cell = (uint32_t)((k * P.ny + j) * P.nx + i);
-            const bool clear = kFactored && __float_as_uint(K) >> 31;
+            bool clear = kFactored && __float_as_uint(K) >> 31;
+            if (kFactored && !clear && P.cell_mask) {
+                // a cloud-free fine cell of a cloudy acceleration cell holds a
+                // zero record too: its bit, from a small array that stays in
+                // the L2, spares the gather of a whole line of records
+                const uint32_t t = (uint32_t)(((k - bk * P.bz) * P.by + (j - bj * P.by)) * P.bx + (i - bi * P.bx));
+                const uint32_t b = (uint32_t)((bk * P.my + bj) * P.mx + bi);
+                clear = !((P.cell_mask[(size_t)b * P.mask_words + (t >> 5)] >> (t & 31)) & 1u);
+            }
             K = fabsf(K);
             const Local L = local_props<kFactored>(P, gp, cell, k, clear);
             const float iK = rcp(K);
@@ -788,6 +801,29 @@ __global__ void pack_cloud_kernel(const float* __restrict__ kc, const float* __r
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const float k = kc[i];
         out[i] = make_float4(k, k * (1.0f - om[i]), g[i], 0.0f);
+    }
+}
+
+// Factored medium: the cloud-cell mask of the tracer, one 32-bit word per
+// thread: bit s of word q of acceleration cell b is fine cell t = 32 q + s of
+// that cell (x fastest, then y, then z), set where k_ext_cloud != 0 (a cell
+// whose bit is clear has the record (0, 0, g, 0), whose g is never used).
+__global__ void cell_mask_kernel(const float* __restrict__ kc, uint32_t* __restrict__ mask, int nx, int ny, int bx,
+                                 int by, int bz, int mx, int my, int words, size_t n) {
+    const int nb = bx * by * bz;
+    for (size_t w = blockIdx.x * (size_t)blockDim.x + threadIdx.x; w < n; w += (size_t)gridDim.x * blockDim.x) {
+        const size_t b = w / words;
+        const int q = (int)(w % words);
+        const int bi = (int)(b % mx), bj = (int)((b / mx) % my), bk = (int)(b / ((size_t)mx * my));
+        uint32_t m = 0;
+        for (int s = 0; s < 32; ++s) {
+            const int t = 32 * q + s;
+            if (t >= nb) break;
+            const int ix = t % bx, jy = (t / bx) % by, kz = t / (bx * by);
+            const size_t cell = ((size_t)(bk * bz + kz) * ny + (size_t)(bj * by + jy)) * nx + (size_t)(bi * bx + ix);
+            if (kc[cell] != 0.0f) m |= 1u << s;
+        }
+        mask[w] = m;
     }
 }
 
@@ -1074,9 +1110,12 @@ rt3d_status zero_u64(unsigned long long* p, size_t n, hipStream_t st) {
 //   cells    packed per-cell records [ncell] float4
 //   gas      factored only: (k_gas, gas k_abs) [ngp][nz] float2
 //   layer    factored only: per-level cloud maxima [nz][my][mx] uint32
+//   mask     factored only: cloud-cell bits [nmaj][mask_words] uint32
 struct Layout {
-    size_t meta, maj, cells, gas, layer, total;
+    size_t meta, maj, cells, gas, layer, mask, total;
 };
+
+int mask_words_of(const Shape& s) { return (s.bx * s.by * s.bz + 31) / 32; }
 
 Layout layout_of(const Shape& s, int ngp, bool factored) {
     Layout l;
@@ -1087,12 +1126,14 @@ Layout layout_of(const Shape& s, int ngp, bool factored) {
     off += align256(sizeof(float) * s.nmaj * ngp);
     l.cells = off;
     off += align256(sizeof(float4) * s.ncell);
-    l.gas = l.layer = 0;
+    l.gas = l.layer = l.mask = 0;
     if (factored) {
         l.gas = off;
         off += align256(sizeof(float2) * (size_t)ngp * s.nz);
         l.layer = off;
         off += align256(sizeof(uint32_t) * (size_t)s.nz * s.my * s.mx);
+        l.mask = off;
+        off += align256(sizeof(uint32_t) * s.nmaj * (size_t)mask_words_of(s));
     }
     l.total = off;
     return l;
@@ -1167,6 +1208,7 @@ struct Launch {
     float4* cells;
     float2* gas;
     uint32_t* layer;
+    uint32_t* mask;
     TraceParams P;
 };
 
@@ -1213,6 +1255,7 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
     L->cells = (float4*)(L->ws + lay.cells);
     L->gas = factored ? (float2*)(L->ws + lay.gas) : nullptr;
     L->layer = factored ? (uint32_t*)(L->ws + lay.layer) : nullptr;
+    L->mask = factored ? (uint32_t*)(L->ws + lay.mask) : nullptr;
     unsigned long long* pass_first = (unsigned long long*)(L->ws + lay.meta);
     unsigned long long* rem_first = pass_first + ngp + 1;
     unsigned long long* gp_col = rem_first + ngp + 1;
@@ -1236,6 +1279,8 @@ rt3d_status prepare(const rt3d_grid* grid, int ngp, const uint64_t* photons, con
     P.gas = L->gas;
     P.albedo = albedo;
     P.majorant = L->maj;
+    P.cell_mask = (o.flags & RT3D_FLAG_CELL_MASK) ? L->mask : nullptr;
+    P.mask_words = factored ? mask_words_of(s) : 0;
     schedule_of(s, ngp, photons, o, pass_first, rem_first, gp_col, &P.sched);
     P.abs_dir = (unsigned long long*)out->abs_dir;
     P.abs_dif = (unsigned long long*)out->abs_dif;
@@ -1516,6 +1561,10 @@ rt3d_status rt3d_trace_batched(const rt3d_grid* grid, int32_t n_gpoints, const r
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(pack_gas_kernel, dim3(grid_for(ngas)), dim3(256), 0, hs, medium->k_gas, medium->ssa_gas,
                        L.gas, ngas);
+    HIP_TRY(hipGetLastError());
+    const size_t nmask = L.P.cell_mask ? L.s.nmaj * (size_t)L.P.mask_words : 0;
+    if (nmask) hipLaunchKernelGGL(cell_mask_kernel, dim3(grid_for(nmask, 256, 16384)), dim3(256), 0, hs, medium->k_cloud, L.mask,
+                       L.s.nx, L.s.ny, L.s.bx, L.s.by, L.s.bz, L.s.mx, L.s.my, L.P.mask_words, nmask);
     HIP_TRY(hipGetLastError());
     const size_t nlayer = (size_t)L.s.nz * L.s.my * L.s.mx;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(nlayer)), dim3(256), 0, hs, L.layer, nlayer, 0u);

@@ -23,6 +23,7 @@ OK, EINVAL, EDOMAIN, EDEVICE, ETOOBIG = 0, 1, 2, 3, 4
 NOALLOC_SCRATCH_BYTES = 32 << 20  # RT3D_NOALLOC_SCRATCH_BYTES
 FLAG_ACCUMULATE, FLAG_VALIDATE, FLAG_TIME, FLAG_NO_MERGE, FLAG_SOBOL_ENTRY = 0x1, 0x2, 0x4, 0x8, 0x10
 FLAG_WAVE_AGGREGATE = 0x20
+FLAG_CELL_MASK = 0x40
 LEDGER = ("incoming", "toa", "atm_dir", "atm_dif", "sfc", "rr_gain", "rr_loss", "lost")
 STATS = ("photons", "collisions", "null", "scat_gas", "scat_cloud", "surface", "escape",
          "rr_kill", "rr_survive", "crossings", "absorbed", "capped")
@@ -340,7 +341,7 @@ def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: 
                   brick=(8, 8, 8), diffuse_fraction: float = 0.0, rr_threshold: float = 0.5,
                   accumulate: bool = False, validate: bool = False, timed: bool = False, max_iters: int = 0,
                   grid_blocks: int = 0, max_walk: int = 0, pool_photons: int = 0, refill_lanes: int = 0,
-                  merge: bool = True, tile=(0, 0), wave_aggregate: bool = False,
+                  merge: bool = True, tile=(0, 0), wave_aggregate: bool = False, cell_mask: bool = False,
                   sobol_entry: bool = False, gpoint_diffuse: Optional[torch.Tensor] = None,
                   out: Optional[dict] = None, workspace: Optional[torch.Tensor] = None, stream=None) -> dict:
     """rt3d_trace_batched: broadband raw tallies of all g-points in one launch.
@@ -359,7 +360,7 @@ def trace_batched(dm: DeviceBatchedMedium, sza: float, azimuth: float, photons: 
             raise ValueError("gpoint_diffuse needs one value per g-point")
     flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_VALIDATE if validate else 0) | \
             (FLAG_TIME if timed else 0) | (0 if merge else FLAG_NO_MERGE) | (FLAG_SOBOL_ENTRY if sobol_entry else 0) | \
-        (FLAG_WAVE_AGGREGATE if wave_aggregate else 0)
+        (FLAG_WAVE_AGGREGATE if wave_aggregate else 0) | (FLAG_CELL_MASK if cell_mask else 0)
     opt = options(brick, diffuse_fraction, rr_threshold, flags, max_iters, 0, grid_blocks, max_walk=max_walk,
                   pool_photons=pool_photons, refill_lanes=refill_lanes, tile=tile)
     gs = grid_struct(grid)

@@ -5,7 +5,7 @@ Bitwise: one batched launch equals the sum of single-g-point batched
 launches (keys seed + n); every launch option (crossings per iteration,
 LDS staging, photon pool, tally merging, wave-aggregated atomics, grid
 size, schedule tile) leaves the uint64
-tallies unchanged.  Statistical: the broadband tallies agree with the FP64
+tallies unchanged, and so does the cloud-cell mask.  Statistical: the broadband tallies agree with the FP64
 oracle run per g-point on the materialised fields and summed."""
 import sys
 
@@ -129,6 +129,29 @@ def test_schedule_tiles_do_not_change_tallies(rt3d):
         rt3d.trace(df, wl.sza, wl.azimuth, n, 5, brick=wl.brick, tile=(3, 4))
 
 
+def test_cell_mask_does_not_change_tallies(rt3d):
+    """Skipping the record gather in cloud-free cells of acceleration cells
+    with cloud (the cloud-cell mask) changes nothing: the same uint64
+    tallies, ledger and counters as gathering at every tentative collision,
+    for cubic and flat acceleration cells (1, 2 and 16 mask words per
+    cell)."""
+    bw = small_batch(n_gp=6, photons=1 << 16, seed=13)
+    m = bw.medium
+    dm = rt3d.DeviceBatchedMedium.from_host(m)
+    nz, ny, nx = m.k_cloud.shape
+    for brick in [(4, 4, 4), (8, 8, 8), (2, 4, 8), (8, 2, 1)]:
+        bx, by, bz = brick
+        cells = m.k_cloud.reshape(nz // bz, bz, ny // by, by, nx // bx, bx) > 0
+        cloudy_brick = cells.any(axis=(1, 3, 5))
+        clear_in_cloudy = (~cells).sum(axis=(1, 3, 5))[cloudy_brick].sum()
+        assert clear_in_cloudy > 0.1 * cloudy_brick.sum() * bx * by * bz, brick
+        ref = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 7, brick=brick))
+        got = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 7, brick=brick, cell_mask=True))
+        ledger_ok(got, int(np.sum(bw.photons)))
+        for k in ARRAYS + ("ledger", "stats"):
+            assert np.array_equal(ref[k], got[k]), (k, brick)
+
+
 def test_batched_parity_vs_oracle(rt3d):
     """Broadband tallies of 6 g-points (gas optical depth 1e-3..50) vs the
     oracle traced per g-point on materialised fields, 64 batches each.  The
@@ -224,6 +247,20 @@ def test_autotuner_picks_valid_options(rt3d, tmp_path):
     ref = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 16, 3, brick=res.options["brick"]))
     got = rt3d.to_host(rt3d.trace(df, wl.sza, wl.azimuth, 1 << 16, 3, **res.options))
     assert np.array_equal(ref["abs_dir"], got["abs_dir"])
+
+
+def test_batched_autotuner_tries_the_cell_mask(rt3d, tmp_path):
+    from paper_2208_05247_amd import autotune
+    bw = small_batch()
+    dm = rt3d.DeviceBatchedMedium.from_host(bw.medium)
+    res = autotune.tune_batched(dm, bw.sza, bw.azimuth, bw.photons, sample=1 << 17,
+                                cache_path=str(tmp_path / "c.json"), bricks=[(4, 4, 4)], walks=[0], pools=[256],
+                                refills=[16], grid_mults=(3,), tiles=[(8, 8)])
+    assert any(r.get("cell_mask") for r in res.table)
+    ref = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 3, brick=(4, 4, 4)))
+    got = rt3d.to_host(rt3d.trace_batched(dm, bw.sza, bw.azimuth, bw.photons, 3, **res.options))
+    for k in ARRAYS + ("ledger", "stats"):
+        assert np.array_equal(ref[k], got[k]), k
 
 
 def test_more_than_2_31_photons_in_one_launch(rt3d):

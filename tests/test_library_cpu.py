@@ -90,7 +90,9 @@ def test_workspace_size_host_only(lib):
     assert n == 256 + 256 + 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16
     nb = rt3d.workspace_size_batched(g, 112, o)
     meta = (8 * (3 * 112 + 2) + 255) // 256 * 256
-    assert nb == 256 + meta + 112 * 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16 + 112 * 128 * 8 + 128 * 32 * 32 * 4
+    # + gas tables, per-level cloud maxima, cloud-cell mask (512 bits per brick)
+    assert nb == (256 + meta + 112 * 32 * 32 * 16 * 4 + 256 * 256 * 128 * 16 + 112 * 128 * 8 + 128 * 32 * 32 * 4
+                  + 32 * 32 * 16 * 64)
     assert lib.rt3d_workspace_size_batched(ctypes.byref(rt3d.grid_struct(g)), 0, ctypes.byref(o)) == 0
     assert lib.rt3d_workspace_size_batched(ctypes.byref(rt3d.grid_struct(g)), 257, ctypes.byref(o)) == 0
     bad = rt3d.options(brick=(3, 8, 8))

@@ -35,6 +35,12 @@ HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 HEADLINE = dict(seed=99_999, nx=1024, nz=128, dx=25.0, dz=20.0, sza=60.0, az=0.0, photons=1 << 30)
 HEADLINE_NAME = "batched_cumulus_1024x1024x128_112g"
+# acceleration cell of the headline launch: the least Monte Carlo cost
+# (kernel time x heating-tally variance, from two seeds at the full 2^30
+# photons) of a same-box sweep; relative cost 8x8x8 1.000, 8x8x16 1.005,
+# 4x8x8 1.014, 16x16x16 1.017, 8x8x4 1.028, 16x16x8 1.028, 4x4x8 1.051,
+# 4x4x4 1.119.  Finer cells trace a photon faster (4x4x8 1472 ms against
+# 1557 ms) but deposit absorption at fewer tentative collisions
 HEADLINE_BRICK = (8, 8, 8)
 # entry tile of the photon schedule for the headline launch (order only, the
 # tallies are bitwise those of any other tile): the fastest of a same-box
@@ -109,10 +115,52 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def headline_key(tile) -> str:
+def headline_key(brick, tile) -> str:
     """Workload key of the headline's committed counter summary: the
-    workload and the schedule tile the counters were taken with."""
-    return f"{HEADLINE_NAME}, schedule tile {tile[0]}x{tile[1]}"
+    workload, acceleration cell and schedule tile the counters were taken
+    with."""
+    return f"{HEADLINE_NAME}, brick {brick[0]}x{brick[1]}x{brick[2]}, schedule tile {tile[0]}x{tile[1]}"
+
+
+def parse_brick(text: str):
+    """--brick: one edge (cubic) or bx,by,bz; empty: the headline's."""
+    if not text:
+        return HEADLINE_BRICK
+    v = tuple(int(x) for x in text.split(","))
+    return v * 3 if len(v) == 1 else v
+
+
+CELL_SWEEP = [(8, 8, 8), (4, 4, 8), (8, 8, 4), (4, 8, 8), (8, 8, 16), (16, 16, 8), (4, 4, 4), (16, 16, 16)]
+
+
+def cell_sweep(tr, counts) -> list:
+    """The headline's photons per acceleration cell: kernel ms and the
+    variance of the heating tallies from two seeds (summed squared
+    difference, halved); cost = ms x variance relative to the first cell
+    (time to a given error is proportional to it)."""
+    import torch
+    from paper_2208_05247_amd import autotune, rt3d
+    wl = tr.wl
+    rows, ref = [], None
+    for b in CELL_SWEEP:
+        ws = rt3d.alloc_workspace(rt3d.workspace_size_batched(tr.grid, tr.m.n_gpoints, rt3d.options(brick=b)))
+        kms, heat = [], []
+        for seed in (1, 2):
+            raw = rt3d.trace_batched(tr.dm, wl.sza, wl.azimuth, counts, seed, brick=b, out=tr.out, workspace=ws,
+                                     timed=True, gpoint_diffuse=tr.fd, tile=tr.tile)
+            kms.append(rt3d.last_trace_ms())
+            heat.append(raw["abs_dir"].double() + raw["abs_dif"].double())
+        noise = autotune._noise(heat[0], heat[1])
+        mean_sq = float((0.25 * (heat[0] + heat[1]) ** 2).sum())
+        st = dict(zip(rt3d.STATS, raw["stats"].cpu().tolist()))
+        ms = min(kms)
+        ref = ms * noise if ref is None else ref
+        rows.append({"brick": list(b), "kernel_ms": kms, "relative_variance": noise / mean_sq,
+                     "cost_relative": ms * noise / ref, "events_per_photon": st["collisions"] / st["photons"]})
+        log(json.dumps(rows[-1]))
+        del ws, heat
+        torch.cuda.empty_cache()
+    return rows
 
 
 def headline_scene():
@@ -448,7 +496,8 @@ def main():
     ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-5 %% evaluation")
     ap.add_argument("--ttr-reference", type=int, default=TTR_REFERENCE_PER_COLUMN,
                     help="photons per column of the time-to-5 %% reference")
-    ap.add_argument("--brick", type=int, default=0, help="cubic brick edge of the headline (0 = default)")
+    ap.add_argument("--brick", default="", help="acceleration cell of the headline: one edge or bx,by,bz "
+                                               "(default: the headline's)")
     ap.add_argument("--budget-s", type=float, default=540.0,
                     help="wall-clock budget of the whole run: optional legs that would not fit are skipped "
                          "(and say so) so that the JSON line is always printed")
@@ -457,6 +506,9 @@ def main():
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the memory-access ceiling probe on the headline footprint (prints its JSON)")
     ap.add_argument("--les-only", action="store_true", help="only the 256x256x128 single g-point leg")
+    ap.add_argument("--cell-sweep", action="store_true",
+                    help="only the headline's photons per acceleration cell: kernel time, tally variance and "
+                         "their product (prints its JSON)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run one plain device copy of this many bytes (for HBM counter scaling)")
     ap.add_argument("--calibrate-gathers", type=int, default=0,
@@ -503,19 +555,21 @@ def main():
 
     log("headline scene ...")
     wl = headline_scene()
-    brick = (args.brick,) * 3 if args.brick else HEADLINE_BRICK
+    brick = parse_brick(args.brick)
     tr = ex.Tracer(wl, brick=brick, tile=HEADLINE_TILE if brick == HEADLINE_BRICK else (0, 0))
     counts = ex.multinomial_counts(tr.shares, HEADLINE["photons"], 5)
     if args.probe_only:
         print(json.dumps({"access_ceiling": access_ceiling(tr.grid.ncell, 5.0e10, 11)}), flush=True)
+        return
+    if args.cell_sweep:
+        print(json.dumps({"cell_sweep": cell_sweep(tr, counts)}), flush=True)
         return
     log("headline steps ...")
     hl = headline(tr, counts, args.steps, args.warmup)
     tot = hl["stats"]
     events = tot["collisions"] + tot["surface"]
     mean_kms = sum(hl["kernel_ms"]) / len(hl["kernel_ms"])
-    traffic = measured_traffic("trace_kernel_batched_cumulus_1024x1024x128.md", headline_key(tr.tile)) \
-        if brick == HEADLINE_BRICK else None
+    traffic = measured_traffic("trace_kernel_batched_cumulus_1024x1024x128.md", headline_key(brick, tr.tile))
     g = tr.grid
     res = {
         "metric": METRIC,

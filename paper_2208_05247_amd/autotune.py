@@ -7,11 +7,20 @@ the tally mode (merging a lane's deposits, wave-aggregated atomics), for
 batched launches the cloud-cell mask, and the entry tile of the photon
 schedule from short
 calibration runs (the tile matters only when the sample holds full passes
-over the columns, i.e. at least as many photons per g-point as columns).  The
-objective is tracing-kernel time per photon (HIP events around the kernel),
-not events/s: looser majorants inflate the event count without doing more
-useful work.  Every candidate traces the same photons through the same
-fields, so the choice changes only speed, never the estimator's expectation.
+over the columns, i.e. at least as many photons per g-point as columns).
+Every candidate traces the same photons through the same fields, so the
+choice never changes the estimator's expectation.  All options but the
+acceleration cell only reorder work (the uint64 tallies are bitwise the
+same), and their objective is tracing-kernel time (HIP events around the
+kernel).  The acceleration cell also changes the variance: every tentative
+collision, null ones included, deposits absorbed weight, so a looser
+majorant costs more events per photon but samples the absorption more
+often.  Its objective is therefore the Monte Carlo cost, kernel time times
+the variance of the heating tallies (their summed squared difference between
+two runs with different seeds, halved): the time to a given error is
+proportional to it (error ~ N^-1/2, time ~ N, sec. 3.2).  Measured on the
+1024x1024x128 field: 4x4x8 cells trace a photon 6 % faster than 8x8x8 but
+with 12 % more variance.
 
 Results are cached in a JSON file keyed by device, library build, grid,
 sun geometry and a fingerprint of the fields.
@@ -81,25 +90,47 @@ def _store_cache(path, cache):
     os.replace(tmp, path)
 
 
-def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=None, pools=None,
-            grid_mults=(1,), try_merge=True, refills=None, tiles=None, try_cell_mask=False):
-    """Staged coordinate search; run(opts) returns kernel ms for `sample` photons."""
+def _noise(h0: torch.Tensor, h1: torch.Tensor) -> float:
+    """Summed variance of one run's heating tallies from two independent
+    runs: sum over cells of (h0 - h1)^2 / 2."""
+    return float(((h0 - h1) ** 2).sum()) / 2.0
+
+
+def _search(run: Callable[..., float], heat: Callable[[], torch.Tensor], grid, sample: int, bricks=None,
+            walks=None, pools=None, grid_mults=(1,), try_merge=True, refills=None, tiles=None,
+            try_cell_mask=False):
+    """Staged coordinate search; run(opts, k) traces `sample` photons with
+    seed offset k and returns the kernel ms, heat() the heating tallies of
+    the last run (FP64, abs_dir + abs_dif)."""
     table = []
 
+    def row(opts, **v):
+        table.append({**{k: (list(x) if isinstance(x, tuple) else x) for k, x in opts.items()}, **v})
+
     def measure(opts):
-        ms = min(run(opts) for _ in range(2))
-        table.append({**{k: (list(v) if isinstance(v, tuple) else v) for k, v in opts.items()},
-                      "kernel_ms": ms, "ms_per_photon": ms / sample})
+        ms = min(run(opts, 0) for _ in range(2))
+        row(opts, kernel_ms=ms, ms_per_photon=ms / sample)
         return ms
 
+    def cost(opts):
+        """Kernel ms x tally variance (two seeds)."""
+        ms0 = run(opts, 0)
+        h0 = heat()
+        ms1 = run(opts, 1)
+        ms = min(ms0, ms1)
+        noise = _noise(h0, heat())
+        del h0
+        row(opts, kernel_ms=ms, ms_per_photon=ms / sample, tally_variance=noise, cost=ms * noise)
+        return ms, ms * noise
+
     best = {"brick": (8, 8, 8) if _divides(grid, (8, 8, 8)) else (1, 1, 1)}
-    best_ms = float("inf")
+    best_cost = best_ms = float("inf")
     for b in (bricks or BRICKS):
         if not _divides(grid, b):
             continue
-        ms = measure({"brick": b})
-        if ms < best_ms:
-            best_ms, best = ms, {"brick": b}
+        ms, c = cost({"brick": b})
+        if c < best_cost:
+            best_cost, best_ms, best = c, ms, {"brick": b}
     for wk in (walks or WALKS):
         if wk == 0:
             continue
@@ -121,7 +152,7 @@ def _search(run: Callable[[dict], float], grid, sample: int, bricks=None, walks=
         ms = measure(o)
         if ms < best_ms:
             best_ms, best = ms, o
-    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count if grid_mults else 0
     for m in grid_mults:   # persistent workgroups per CU below full occupancy
         o = {**best, "grid_blocks": int(ncu * m)}
         ms = measure(o)
@@ -160,13 +191,15 @@ def tune_trace(df: "rt3d.DeviceFields", sza: float, azimuth: float, sample: int 
         return TuneResult(_opts_from_json(c["options"]), c["ms_per_photon"], c["table"], cached=True)
     out = rt3d.alloc_tallies(df.grid)
 
-    def run(opts):
-        o = dict(opts)
-        rt3d.trace(df, sza, azimuth, sample, seed, out=out, timed=True, **o)
+    def run(opts, k=0):
+        rt3d.trace(df, sza, azimuth, sample, seed + k, out=out, timed=True, **opts)
         return rt3d.last_trace_ms()
 
+    def heat():
+        return out["abs_dir"].double() + out["abs_dif"].double()
+
     search_kw.setdefault("grid_mults", (1,))
-    best, best_ms, table = _search(run, df.grid, sample, **search_kw)
+    best, best_ms, table = _search(run, heat, df.grid, sample, **search_kw)
     res = TuneResult(best, best_ms / sample, table)
     if cache_path:
         cache[key] = {"options": _opts_to_json(best), "ms_per_photon": res.ms_per_photon, "table": table}
@@ -192,13 +225,16 @@ def tune_batched(dm: "rt3d.DeviceBatchedMedium", sza: float, azimuth: float, pho
         return TuneResult(_opts_from_json(c["options"]), c["ms_per_photon"], c["table"], cached=True)
     out = rt3d.alloc_tallies(dm.grid)
 
-    def run(opts):
-        rt3d.trace_batched(dm, sza, azimuth, share, seed, out=out, timed=True, **opts)
+    def run(opts, k=0):
+        rt3d.trace_batched(dm, sza, azimuth, share, seed + k, out=out, timed=True, **opts)
         return rt3d.last_trace_ms()
+
+    def heat():
+        return out["abs_dir"].double() + out["abs_dif"].double()
 
     search_kw.setdefault("grid_mults", (3, 4))
     search_kw.setdefault("try_cell_mask", True)
-    best, best_ms, table = _search(run, dm.grid, sample, **search_kw)
+    best, best_ms, table = _search(run, heat, dm.grid, sample, **search_kw)
     res = TuneResult(best, best_ms / sample, table)
     if cache_path:
         cache[key] = {"options": _opts_to_json(best), "ms_per_photon": res.ms_per_photon, "table": table}

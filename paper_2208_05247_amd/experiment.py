@@ -477,6 +477,11 @@ def main():
     ap.add_argument("--save-weights", default=None, help="store the trained weights here (.npz)")
     ap.add_argument("--weights", default=None, help="evaluate these stored weights instead of training")
     ap.add_argument("--no-eval", action="store_true", help="train (and save) only")
+    ap.add_argument("--init-weights", default=None,
+                    help="start training from these stored weights (fresh Adam moments) instead of random ones")
+    ap.add_argument("--first-scene", type=int, default=0,
+                    help="seed of the first training scene (a continued run takes scenes it has not seen)")
+    ap.add_argument("--lr", type=float, default=1e-3, help="peak learning rate of the cosine schedule")
     ap.add_argument("--direct-feature", action="store_true",
                     help="give the network a fifth input: the deterministic direct-beam heating of the gray medium")
     args = ap.parse_args()
@@ -494,14 +499,20 @@ def main():
         res["weights"] = winfo
         train_s = None
     else:
-        net = dn.Denoiser(base=32, seed=0, n_in=5 if args.direct_feature else 4)
+        if args.init_weights:
+            net, winfo = load_denoiser(args.init_weights)
+            res["init_weights"] = winfo
+        else:
+            net = dn.Denoiser(base=32, seed=0, n_in=5 if args.direct_feature else 4)
         log(f"denoiser parameters: {net.n_params()}")
         t0 = time.perf_counter()
         low = tuple(int(v) for v in args.train_low.split(","))
         losses, step_s = train(net, nf, args.steps_per_field, tr_nx, nz, dx, dz, low=low,
-                               high=2048 if args.quick else args.target_photons, tod_entry=not args.sun_entry)
+                               high=2048 if args.quick else args.target_photons, lr=args.lr,
+                               seed0=args.first_scene, tod_entry=not args.sun_entry)
         train_s = time.perf_counter() - t0
-        res.update({"train_fields": nf, "train_steps": len(losses), "train_seconds": train_s,
+        res.update({"train_fields": nf, "first_scene": args.first_scene, "lr": args.lr,
+                    "train_steps": len(losses), "train_seconds": train_s,
                     "ms_per_train_step": 1e3 * step_s, "target_photons_per_column": args.target_photons,
                     "final_train_loss": float(np.mean(losses[-20:])), "train_grid": [tr_nx, tr_nx, nz]})
         if args.save_weights:

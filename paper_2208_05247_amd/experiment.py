@@ -41,14 +41,17 @@ from . import denoise as dn
 from . import rt3d
 from . import synthetic as syn
 
-# Denoiser weights trained by `python -m paper_2208_05247_amd.experiment
-# --save-weights <path> --no-eval` with the default recipe (800 scenes of
-# 128 x 128 x 128 cells of 25 x 25 x 20 m, two-stream entry, one
-# 32768-photon target and 16 noisy inputs of 128..768 photons per column per
-# scene; 858 s on one MI355X); BF16 weights and FP32 biases, identified by
-# the sha256 of their contents (training is bitwise reproducible).
+# Denoiser weights trained in two runs of `python -m
+# paper_2208_05247_amd.experiment ... --no-eval`: first `--save-weights
+# <a>` with the default recipe (800 scenes of 128 x 128 x 128 cells of
+# 25 x 25 x 20 m, two-stream entry, one 32768-photon target and 16 noisy
+# inputs of 128..768 photons per column per scene, peak learning rate 1e-3;
+# 858 s on one MI355X; contents sha256 bba98230...), then `--init-weights
+# <a> --first-scene 800 --lr 3e-4 --save-weights <b>` (800 further scenes,
+# fresh Adam moments; 856 s).  BF16 weights and FP32 biases, identified by
+# the sha256 of their contents (each training run is bitwise reproducible).
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "denoiser_25x25x20m.npz")
-WEIGHTS_SHA256 = "bba98230aca74cde41683813c7062c67337b372335ee19d3a53e2fc049a03eef"
+WEIGHTS_SHA256 = "aa075f64c1fe799c885aa0fd312e96ab5f891c3d1fe67f97c3a8e77eab2eb3d1"
 
 F_TOD = 1000.0     # W m^-2, nominal total (direct + diffuse) downward flux at the domain top
 CP = 1004.0        # J kg^-1 K^-1
@@ -407,11 +410,20 @@ def evaluate(net: dn.Denoiser, wl, ref_per_col: int, sweep=(16, 64, 256, 1024, 4
         res["denoised_photons_per_column_at_5pct"] = sustained["photons_per_column"]
         res["denoised_time_to_5pct_ms"] = t_dn
         res["speedup"] = t_plain / t_dn
-        res["speedup_small_reference"] = t_plain_s / t_dn
     else:
         res["denoised_photons_per_column_at_5pct"] = None
         res["denoised_time_to_5pct_ms"] = None
         res["speedup"] = None
+    # the same against the smaller reference: its own crossing, its own fit
+    k_s = sustained_below([d["eps_denoised_small_reference"] for d in den], TARGET_EPS)
+    if k_s is not None:
+        t_dn_s = den[k_s]["trace_ms"] + den[k_s]["inference_ms"]
+        res["denoised_photons_per_column_at_5pct_small_reference"] = den[k_s]["photons_per_column"]
+        res["denoised_time_to_5pct_ms_small_reference"] = t_dn_s
+        res["speedup_small_reference"] = t_plain_s / t_dn_s
+    else:
+        res["denoised_photons_per_column_at_5pct_small_reference"] = None
+        res["speedup_small_reference"] = None
     # what the network gains at equal photons: raw vs denoised error
     res["gain_at_equal_photons"] = [{"photons_per_column": d["photons_per_column"],
                                      "eps_raw": d["eps_raw"], "eps_denoised": d["eps_denoised"]} for d in den]

@@ -20,7 +20,7 @@ the variance of the heating tallies (their summed squared difference between
 two runs with different seeds, halved): the time to a given error is
 proportional to it (error ~ N^-1/2, time ~ N, sec. 3.2).  Measured on the
 1024x1024x128 field: 4x4x8 cells trace a photon 6 % faster than 8x8x8 but
-with 12 % more variance.
+with 9 % more variance (5 % more cost).
 
 Results are cached in a JSON file keyed by device, library build, grid,
 sun geometry and a fingerprint of the fields.

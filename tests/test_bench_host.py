@@ -57,6 +57,20 @@ def test_committed_traffic_summaries_name_their_workload():
             assert "source_sha256_16" in f and "workload" in f, name
 
 
+def test_headline_workload_key_and_cell_argument():
+    """The headline summary is keyed by workload, acceleration cell and
+    schedule tile, so counters taken with another cell are not reported;
+    --brick takes one edge or three."""
+    key = bench.headline_key((8, 8, 8), (128, 128))
+    assert key == bench.HEADLINE_NAME + ", brick 8x8x8, schedule tile 128x128"
+    assert bench.headline_key((4, 4, 8), (128, 128)) != key
+    assert bench.parse_brick("") == bench.HEADLINE_BRICK
+    assert bench.parse_brick("4") == (4, 4, 4)
+    assert bench.parse_brick("4,4,8") == (4, 4, 8)
+    f = bench.profile_fields("trace_kernel_batched_cumulus_1024x1024x128.md")
+    assert f["workload"] == bench.headline_key(bench.HEADLINE_BRICK, bench.HEADLINE_TILE)
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
